@@ -1,0 +1,245 @@
+"""Pins of the oracle's fan-beam model against exact geometry.
+
+* tau -> 0: the CNSF entry must equal the exact chord of the ray through the
+  pixel (Theorem 2 and its corollary are exact, eq. (16)).
+* parallel beam: the entry must equal area(strip of the cell inside the
+  pixel) / tau exactly (Theorem 1, eq. (11); area by Sutherland-Hodgman
+  clipping and Gauss's formula, eq. (8)).
+* fan beam with blur: CNSF approximates the reference projector (exact chord
+  averaged over the cell, Sec. V) to the accuracy the paper claims, and the
+  approximation improves as the source moves away (Sec. V-B).
+* a uniform disk projects to the closed-form bin-averaged 2 sqrt(r^2 - d^2).
+* adjoint identity, linearity, rotation symmetry, mass, pruning.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import exact_geometry as eg
+from paper_1907_10526_amd import phantoms, workloads
+
+
+def test_zero_blur_entry_is_exact_chord(oracle_mod):
+    nx = ny = 12
+    rng = np.random.default_rng(0)
+    angs = np.concatenate([[0.0, math.pi / 2, math.pi / 4, math.pi, 1.5 * math.pi],
+                           rng.uniform(0, 2 * math.pi, 6)])
+    spacing, dsc, dsd, n_det = 0.7, 40.0, 80.0, 64
+    g = oracle_mod.Geometry(nx, ny, 1.0, dsc, dsd, angs, n_det, 0.0, det_spacing=spacing)
+    worst, hits = 0.0, 0
+    for v, th in enumerate(angs):
+        for i in range(nx):
+            for j in range(ny):
+                lo, hi = eg.pixel_box(i, j, nx, ny, 1.0)
+                for m in range(n_det):
+                    s = (m - 0.5 * (n_det - 1)) * spacing
+                    ch = eg.fan_chord(th, dsc, dsd, s, lo, hi)
+                    worst = max(worst, abs(ch - g.entry(v, m, i, j)))
+                    hits += ch > 0
+    assert hits > 2000
+    assert worst < 1e-12, worst
+
+
+def test_parallel_entry_is_exact_strip_area(oracle_mod):
+    n, n_det, tau = 8, 24, 0.8
+    rng = np.random.default_rng(1)
+    angs = np.concatenate([[0.0, math.pi / 4, math.pi / 2, 0.3], rng.uniform(0, 2 * math.pi, 6)])
+    g = oracle_mod.Geometry(n, n, 1.0, 50.0, 100.0, angs, n_det, tau, mode=oracle_mod.PARALLEL)
+    worst = 0.0
+    for v, th in enumerate(angs):
+        e = np.array([math.sin(th), -math.cos(th)])
+        for i in range(n):
+            for j in range(n):
+                lo, hi = eg.pixel_box(i, j, n, n, 1.0)
+                for m in range(n_det):
+                    s = (m - 0.5 * (n_det - 1)) * tau
+                    ref = eg.strip_pixel_area(e, s - 0.5 * tau, s + 0.5 * tau, lo, hi) / tau
+                    worst = max(worst, abs(ref - g.entry(v, m, i, j)))
+    assert worst < 1e-13, worst
+
+
+def test_parallel_mass_is_pixel_area(oracle_mod):
+    n, n_det, tau, pix = 8, 40, 0.6, 1.3
+    angs = np.linspace(0.0, math.pi, 11)
+    g = oracle_mod.Geometry(n, n, pix, 50.0, 100.0, angs, n_det, tau, mode=oracle_mod.PARALLEL)
+    for v in range(len(angs)):
+        for i, j in [(0, 0), (3, 4), (7, 2)]:
+            tot = sum(tau * g.entry(v, m, i, j) for m in range(n_det))
+            assert tot == pytest.approx(pix * pix, abs=1e-13)
+
+
+def _ref_error(oracle_mod, n, dsc, dsd, tau, angs, pixels, pad=8):
+    n_det = 2 * int(math.ceil(0.75 * n * dsd / dsc / tau)) + pad
+    g = oracle_mod.Geometry(n, n, 1.0, dsc, dsd, angs, n_det, tau)
+    worst = 0.0
+    for v, th in enumerate(angs):
+        for i, j in pixels:
+            lo, hi = eg.pixel_box(i, j, n, n, 1.0)
+            for m in range(n_det):
+                s = (m - 0.5 * (n_det - 1)) * tau
+                r = eg.ref_entry(th, dsc, dsd, s, tau, lo, hi)
+                if r == 0.0 and g.entry(v, m, i, j) == 0.0:
+                    continue
+                worst = max(worst, abs(r - g.entry(v, m, i, j)))
+    return worst
+
+
+def test_cnsf_close_to_reference_projector(oracle_mod):
+    """e(u) of eq. (19), maximised over views and pixels: the CNSF model is
+    within 1e-3 of the exact blurred projection on the small scan's geometry
+    and gets closer as the source-detector distance grows."""
+    angs = np.linspace(0.0, 2 * math.pi, 13)[:-1] + 0.05
+    pix = [(0, 0), (7, 7), (3, 5), (7, 0)]
+    e_small = _ref_error(oracle_mod, 8, 128.0, 256.0, 1.5, angs, pix)
+    e_mid = _ref_error(oracle_mod, 8, 200.0, 400.0, 0.5, angs, pix)
+    e_far = _ref_error(oracle_mod, 8, 1000.0, 1500.0, 1.0, angs, pix)
+    assert e_small < 1e-3, e_small
+    assert e_far < e_mid < e_small, (e_small, e_mid, e_far)
+    assert e_far < 2e-4
+
+
+def test_cnsf_reference_on_small_scan_grid(oracle_mod):
+    s = workloads.SMALL
+    g = oracle_mod.Geometry(**s.kwargs())
+    angs = s.view_angles()
+    worst = 0.0
+    for v in (0, 11, 30, 58):
+        for i, j in [(0, 0), (63, 63), (20, 41), (32, 31), (5, 60)]:
+            lo, hi = eg.pixel_box(i, j, s.n, s.n, 1.0)
+            for m in range(s.n_det):
+                e = g.entry(v, m, i, j)
+                sm = (m - 0.5 * (s.n_det - 1)) * s.det_width
+                if e == 0.0 and abs(sm - eg.corner_shadows(angs[v], s.dsc, s.dsd, lo, hi)[0]) > 6:
+                    continue
+                r = eg.ref_entry(angs[v], s.dsc, s.dsd, sm, s.det_width, lo, hi)
+                worst = max(worst, abs(r - e))
+    assert worst < 2e-3, worst
+
+
+def test_fan_mass_close_to_pixel_area(oracle_mod):
+    """sum_m tau'_m A_(m,k) ~ delta^2 for pixels fully seen by the detector:
+    the effective blur tiles the line at the pixel's depth (eq. (17))."""
+    s = workloads.SMALL
+    g = oracle_mod.Geometry(**s.kwargs())
+    worst = 0.0
+    for v in (0, 7, 13, 22, 45, 80):
+        for i, j in [(0, 0), (31, 32), (63, 0), (10, 50), (40, 20), (63, 63)]:
+            ms = [m for m in range(s.n_det) if g.entry(v, m, i, j) != 0.0]
+            if ms[0] == 0 or ms[-1] == s.n_det - 1:
+                continue  # truncated by the detector edge
+            tot = sum(g.entry_terms(v, m, i, j)[3] * g.entry(v, m, i, j) for m in ms)
+            worst = max(worst, abs(tot - 1.0))
+    assert worst < 2e-3, worst
+
+
+def test_disk_projection_closed_form(oracle_mod):
+    s = workloads.SMALL
+    angs = s.view_angles()[:12]
+    g = oracle_mod.Geometry(s.n, s.n, 1.0, s.dsc, s.dsd, angs, s.n_det, s.det_width)
+    ref = np.array([[eg.disk_fan_projection(a, s.dsc, s.dsd, (m - 0.5 * (s.n_det - 1)) * s.det_width,
+                                            s.det_width, 24.0) for m in range(s.n_det)] for a in angs])
+    y = g.forward(phantoms.disk(s.n, 24.0, 1.0).astype(np.float64))
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    # halving the pixel with the radius fixed in length units shrinks the
+    # pixelisation error
+    g2 = oracle_mod.Geometry(2 * s.n, 2 * s.n, 0.5, s.dsc, s.dsd, angs, s.n_det, s.det_width)
+    y2 = g2.forward(phantoms.disk(2 * s.n, 48.0, 0.5).astype(np.float64))
+    err2 = np.linalg.norm(y2 - ref) / np.linalg.norm(ref)
+    assert err < 1e-2, err
+    assert err2 < 0.4 * err, (err, err2)
+
+
+def test_adjoint_identity(oracle_mod):
+    s = workloads.SMALL
+    g = oracle_mod.Geometry(**s.kwargs())
+    c = phantoms.uniform((s.n, s.n), 11).astype(np.float64)
+    y = phantoms.uniform((s.n_views, s.n_det), 12).astype(np.float64)
+    lhs = float(np.sum(g.forward(c) * y))
+    rhs = float(np.sum(c * g.back(y)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs), (lhs, rhs)
+
+
+def test_linearity_and_zero(oracle_mod):
+    s = workloads.SMALL
+    g = oracle_mod.Geometry(**s.kwargs())
+    c1 = phantoms.uniform((s.n, s.n), 21).astype(np.float64)
+    c2 = phantoms.uniform((s.n, s.n), 22).astype(np.float64)
+    lhs = g.forward(2.5 * c1 - 0.75 * c2)
+    rhs = 2.5 * g.forward(c1) - 0.75 * g.forward(c2)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(rhs))
+    assert not np.any(g.forward(np.zeros((s.n, s.n))))
+    assert not np.any(g.back(np.zeros((s.n_views, s.n_det))))
+
+
+def test_rotation_symmetry(oracle_mod):
+    """Turning the object and the scanner by 90 degrees together changes
+    nothing: view theta + pi/2 of the rotated image equals view theta."""
+    n, n_det = 16, 40
+    th = np.array([0.3, 1.1, 2.0])
+    c = phantoms.uniform((n, n), 31).astype(np.float64)
+    rot = np.empty_like(c)
+    for j in range(n):
+        for i in range(n):
+            rot[j, i] = c[n - 1 - i, j]  # c'(x, y) = c(y, -x)
+    g0 = oracle_mod.Geometry(n, n, 1.0, 40.0, 90.0, th, n_det, 1.1)
+    g1 = oracle_mod.Geometry(n, n, 1.0, 40.0, 90.0, th + math.pi / 2, n_det, 1.1)
+    a, b = g0.forward(c), g1.forward(rot)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_mirror_symmetry(oracle_mod):
+    """Mirroring x -> -x maps view theta to view pi - theta with the detector
+    axis reversed."""
+    n, n_det = 16, 40
+    th = np.array([0.3, 1.1, 2.0])
+    c = phantoms.uniform((n, n), 32).astype(np.float64)
+    g0 = oracle_mod.Geometry(n, n, 1.0, 40.0, 90.0, th, n_det, 1.1)
+    g1 = oracle_mod.Geometry(n, n, 1.0, 40.0, 90.0, math.pi - th, n_det, 1.1)
+    a = g0.forward(c)
+    b = g1.forward(c[:, ::-1])[:, ::-1]
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+@pytest.mark.parametrize("n,dsc,dsd,tau,nd", [(8, 20.0, 40.0, 1.0, 24), (16, 30.0, 45.0, 0.7, 48),
+                                              (16, 14.0, 40.0, 1.3, 64)])
+def test_pruned_equals_dense(oracle_mod, n, dsc, dsd, tau, nd):
+    rng = np.random.default_rng(n)
+    angs = np.concatenate([[0.0, math.pi / 2, math.pi / 4], rng.uniform(0, 2 * math.pi, 9)])
+    g = oracle_mod.Geometry(n, n, 1.0, dsc, dsd, angs, nd, tau)
+    c = phantoms.uniform((n, n), 41).astype(np.float64)
+    y = phantoms.uniform((len(angs), nd), 42).astype(np.float64)
+    assert np.array_equal(g.forward(c), g.forward(c, dense=True))
+    assert np.array_equal(g.back(y), g.back(y, dense=True))
+
+
+def test_pruned_equals_dense_small_scan(oracle_mod):
+    s = workloads.SMALL
+    g = oracle_mod.Geometry(**s.kwargs())
+    c = workloads.phantom(s).astype(np.float64)
+    assert np.array_equal(g.forward(c), g.forward(c, dense=True))
+
+
+def test_single_outputs_match_full_operators(oracle_mod):
+    s = workloads.SMALL
+    g = oracle_mod.Geometry(**s.kwargs())
+    c = workloads.phantom(s).astype(np.float64)
+    y = phantoms.uniform((s.n_views, s.n_det), 3).astype(np.float64)
+    fy, bz = g.forward(c), g.back(y)
+    for v, m in [(0, 64), (17, 3), (89, 127), (45, 70)]:
+        assert g.forward_ray(c, v, m) == pytest.approx(fy[v, m], rel=1e-13, abs=1e-13)
+    for i, j in [(0, 0), (63, 63), (17, 40)]:
+        assert g.back_pixel(y, i, j) == pytest.approx(bz[j, i], rel=1e-13, abs=1e-13)
+    part = g.forward_views(c, 10, 20)
+    assert np.array_equal(part[10:20], fy[10:20]) and not np.any(part[:10])
+    bsum = g.back_views(y, 0, 40) + g.back_views(y, 40, s.n_views)
+    assert np.max(np.abs(bsum - bz)) <= 1e-12 * np.max(np.abs(bz))
+
+
+def test_count_nonzero_matches_dense_enumeration(oracle_mod):
+    n, nd = 8, 24
+    angs = np.array([0.0, 0.4, math.pi / 2, 2.0])
+    g = oracle_mod.Geometry(n, n, 1.0, 20.0, 40.0, angs, nd, 1.0)
+    dense = sum(g.entry(v, m, i, j) != 0.0 for v in range(len(angs)) for m in range(nd)
+                for i in range(n) for j in range(n))
+    assert g.count_nonzero() == dense

@@ -1,0 +1,62 @@
+"""Pins of the oracle's SIRT iteration.
+
+SIRT is only cited by the paper (Sec. I); the iteration used here is the
+standard simultaneous one, x <- x + lambda C A^T R (y - A x) with
+R = diag(1 / A 1) and C = diag(1 / A^T 1) (zero sums read as zero).  The
+oracle's loop is pinned to that formula written with a dense matrix whose
+entries are assembled one by one, and to two known properties: the iterates
+of consistent data approach the data, and the R-weighted residual never
+grows for 0 < lambda < 2.
+"""
+import math
+
+import numpy as np
+
+from paper_1907_10526_amd import phantoms
+
+
+def _dense_matrix(g, n, nd, nv):
+    A = np.zeros((nv * nd, n * n))
+    for v in range(nv):
+        for m in range(nd):
+            for j in range(n):
+                for i in range(n):
+                    A[v * nd + m, j * n + i] = g.entry(v, m, i, j)
+    return A
+
+
+def _small(oracle_mod):
+    n, nd = 8, 20
+    angs = np.linspace(0, 2 * math.pi, 10, endpoint=False) + 0.1
+    g = oracle_mod.Geometry(n, n, 1.0, 20.0, 40.0, angs, nd, 1.2)
+    return g, n, nd, len(angs)
+
+
+def test_sirt_matches_dense_formula(oracle_mod):
+    g, n, nd, nv = _small(oracle_mod)
+    A = _dense_matrix(g, n, nd, nv)
+    y = phantoms.uniform(nv * nd, 5, 0.0, 2.0).astype(np.float64)
+    row, col = A.sum(axis=1), A.sum(axis=0)
+    R = np.where(row != 0, 1.0 / np.where(row != 0, row, 1.0), 0.0)
+    C = np.where(col != 0, 1.0 / np.where(col != 0, col, 1.0), 0.0)
+    x = np.zeros(n * n)
+    for _ in range(3):
+        x = x + 0.9 * C * (A.T @ (R * (y - A @ x)))
+    got = g.sirt(y.reshape(nv, nd), 3, relaxation=0.9).reshape(-1)
+    assert np.max(np.abs(got - x)) <= 1e-12 * np.max(np.abs(x))
+
+
+def test_sirt_residual_decreases_and_fits_consistent_data(oracle_mod):
+    g, n, nd, nv = _small(oracle_mod)
+    x_true = phantoms.uniform((n, n), 8, 0.0, 1.0).astype(np.float64)
+    y = g.forward(x_true)
+    ones = g.forward(np.ones((n, n)))
+    R = np.where(ones != 0, 1.0 / np.where(ones != 0, ones, 1.0), 0.0)
+    prev = math.inf
+    for it in (1, 2, 4, 8, 16, 32):
+        x = g.sirt(y, it)
+        r = y - g.forward(x)
+        wres = float(np.sum(R * r * r))
+        assert wres <= prev * (1 + 1e-12)
+        prev = wres
+    assert prev < 1e-2 * float(np.sum(R * y * y))
