@@ -1,0 +1,171 @@
+"""Throughput of one CNSF projection pair (forward + back) on one MI355X.
+
+One step = fp_forward of one 512 x 512 FP32 image into 720 views x 1024
+cells (flat-detector fan beam, source-centre 1000, source-detector 1500,
+cell width 1) followed by fp_back of one 720 x 1024 sinogram.  Inputs are
+resident in HBM before timing starts.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 flops of one matrix entry given the per-ray constants:
+# offset 1, s' 2, L 3, tau' 1, tau'/2 1, 12 argument adds, 8 max, 8 signed
+# square-accumulate FMAs (16), normalisation (reciprocal + multiply) 2,
+# accumulate FMA 2.
+FLOPS_PER_ENTRY = 48
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed / dual issue) x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-views", type=int, default=360,
+                   help="views of the workload the FP64 oracle is timed on")
+    return p.parse_args()
+
+
+def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample):
+    """The FP64 oracle (as it is, OpenMP on the host cores) on a bounded sample:
+    forward rows and back-projection partial sums over the first
+    `n_views_sample` views.  Returns the baseline record and the rel-L2 of
+    the GPU against it on that sample."""
+    import oracle
+    og = oracle.Geometry(**scan.kwargs())
+    k = n_views_sample
+    img64 = img.astype(np.float64)
+    sino64 = sino.astype(np.float64)
+    t0 = time.perf_counter()
+    y_ref = og.forward_views(img64, 0, k)[:k]
+    t1 = time.perf_counter()
+    z_ref = og.back_views(sino64, 0, k)
+    t2 = time.perf_counter()
+    frac = k / scan.n_views
+    secs = (t2 - t0) / frac  # seconds per full pair
+    rec = {"value": 1.0 / secs, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"forward rows and back partial sums of views 0..{k - 1} of {scan.n_views} "
+                     f"({t1 - t0:.1f} s + {t2 - t1:.1f} s, FP64), scaled by {scan.n_views}/{k}"}
+    rel = {
+        "forward": float(np.linalg.norm(y_gpu_rows - y_ref) / np.linalg.norm(y_ref)),
+        "back": float(np.linalg.norm(z_gpu_part - z_ref) / np.linalg.norm(z_ref)),
+        "sample_views": k,
+    }
+    return rec, rel
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the projector is not sharded "
+                                   "across GPUs (use --gpus 1)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1907_10526_amd import fanproj, phantoms, workloads
+
+    scan = workloads.MEDIUM
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    geom = fanproj.Geometry(**scan.kwargs())
+    img_np = workloads.phantom(scan)
+    img = torch.from_numpy(img_np).to(dev)
+    sino = torch.empty((scan.n_views, scan.n_det), dtype=torch.float32, device=dev)
+    back = torch.empty((scan.n, scan.n), dtype=torch.float32, device=dev)
+    nnz = geom.count_nonzero()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        geom.forward(img, out=sino)
+        geom.back(sino, out=back)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for k in range(K):
+        ev[k][0].record(stream)
+        geom.forward(img, out=sino)
+        ev[k][1].record(stream)
+        geom.back(sino, out=back)
+        ev[k][2].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    total_ms = start.elapsed_time(stop)
+    fwd_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    bck_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    step_ms = fwd_ms + bck_ms
+    ms_per_step = total_ms / K
+
+    flops = FLOPS_PER_ENTRY * nnz  # per launch (one projection)
+    kernels = {"forward": float(fwd_ms.mean()), "back": float(bck_ms.mean())}
+    dom = max(kernels, key=kernels.get)
+    achieved = flops / (kernels[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "flops_per_launch": flops, "entries_per_launch": nnz,
+                "flops_per_entry": FLOPS_PER_ENTRY,
+                "avg_ms": {k: round(v, 5) for k, v in kernels.items()},
+                "other_kernel_frac": {k: flops / (v * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
+                                      for k, v in kernels.items()}}
+
+    out = {
+        "metric": "projection pairs (A+A^T)/sec at 512^2x720 views",
+        "value": K / (total_ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fan-beam CNSF forward+back, 512x512 image (pixel 1), 720 views over "
+                               "2pi, 1024 flat-detector cells of width 1, source-centre 1000, "
+                               "source-detector 1500, 20 seeded ellipses, batch 1"},
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "wall_s": t_wall,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        k = max(1, min(args.cpu_sample_views, scan.n_views))
+        sino_in = phantoms.uniform((scan.n_views, scan.n_det), 13, 0.0, 1.0)
+        y_rows = geom.forward(img)[:k].cpu().numpy()
+        part = np.zeros_like(sino_in)
+        part[:k] = sino_in[:k]
+        z_part = geom.back(torch.from_numpy(part).to(dev)).cpu().numpy()
+        rec, rel = cpu_baseline(scan, img_np, sino_in, y_rows, z_part, k)
+        out["cpu_baseline"] = rec
+        out["rel_l2_vs_fp64"] = rel
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    geom.close()
+
+
+if __name__ == "__main__":
+    main()

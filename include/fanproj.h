@@ -1,0 +1,149 @@
+/*
+ * fanproj: fan-beam forward and back-projection with the convolutional
+ * non-separable footprint (CNSF) of Zhang & Entezari, "A Convolutional
+ * Forward and Back-Projection Model for Fan-Beam Geometry" (arXiv 1907.10526),
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The system matrix A is never stored (the paper's "on-the-fly, memory-less"
+ * operator, Sec. V-C).  Entry A_{(v,m),k} is the detector-blurred projection of
+ * the indicator of pixel k on the cell m of view v, in closed form (Sec. IV,
+ * eq. (18)):
+ *     A = delta^2 * M_[zeta1, zeta2, tau'](s'),
+ * a centred, unit-mass, 3-direction box spline whose directions are the two
+ * pixel edges projected perpendicular to the ray through the cell centre
+ * (eq. (16)) and the effective blur tau' (eq. (17)): the cell's two edges seen
+ * from the source, perspective-divided and scaled to the pixel's depth along
+ * that ray.  s' is the signed distance of the pixel centre from the ray.
+ *
+ * Geometry (Sec. II-A): view angle t puts the source at
+ * D_sc * (cos t, sin t); the flat detector is perpendicular to that direction
+ * at distance D_sd from the source; its axis is (sin t, -cos t) (the
+ * projection R_{u perp} = [sin t, -cos t] of Sec. III-B).  Cell m is centred at
+ * s_m = (m - (n_det - 1)/2) * det_width on that axis (pitch = width).  Pixel
+ * (i, j) of an nx x ny image is centred at ((i - (nx-1)/2) delta,
+ * (j - (ny-1)/2) delta): columns run along x, rows along y.
+ *
+ * Layouts (device memory, FP32, contiguous):
+ *     image    [batch][ny][nx]          x fastest
+ *     sinogram [batch][n_views][n_det]  detector cell fastest
+ *
+ * Precision: footprint arithmetic and accumulation in FP32; per-view fan
+ * geometry and the pixel-to-ray offsets in FP64 (Sec. IV's closed form is
+ * evaluated in a cancellation-free form, so no FP64 is needed inside it).
+ *
+ * Threading and streams: every call is asynchronous on `stream` (a
+ * hipStream_t; NULL means the legacy default stream) and returns after
+ * launching.  A geometry is immutable after creation apart from the SIRT
+ * weights, which the first fp_sirt_step builds once (guarded); any number of
+ * threads and streams may then share it.  Kernel faults surface at the
+ * caller's next synchronisation, or as FP_ERR_DEVICE from a later call.
+ *
+ * Errors: no exception crosses this interface.  Every function returns an
+ * fp_status; for a non-OK status fp_last_error() gives a message (per calling
+ * thread).  Outputs are left untouched when arguments are rejected.
+ */
+#ifndef FANPROJ_H
+#define FANPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FP_OK = 0,
+    FP_ERR_INVALID_ARG = 1,   /* null pointer, size < 1, non-finite value,
+                                 geometry with a pixel at or behind the source */
+    FP_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed                    */
+    FP_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed            */
+    FP_ERR_UNSUPPORTED = 4    /* valid but beyond this build's limits          */
+} fp_status;
+
+typedef struct fp_geometry fp_geometry;   /* opaque */
+
+/* Create a fan-beam geometry on the current HIP device (Sec. II-A; the
+ * parameter set of Sec. V: image grid, pixel size, source-to-centre and
+ * source-to-detector distances, view angles, detector count, cell width).
+ *
+ *   nx, ny               image columns and rows, >= 1
+ *   pixel_size           delta > 0
+ *   dist_source_center   D_sc; must exceed delta * (sqrt(nx^2 + ny^2)/2 + 1)
+ *                        so that every pixel lies in front of the source
+ *   dist_source_detector D_sd > D_sc (the detector lies beyond the centre)
+ *   n_views, view_angles host array of n_views finite angles in radians; it
+ *                        is copied, the caller keeps ownership
+ *   n_det, det_width     cell count >= 1 and width (= pitch) > 0
+ *   out                  receives the handle; release it with
+ *                        fp_geometry_destroy
+ *
+ * The per-view and per-ray tables are computed on the host in FP64 and copied
+ * to the device once; the call synchronises with the device.  Returns
+ * FP_ERR_INVALID_ARG for the cases above, FP_ERR_OUT_OF_MEMORY if the tables
+ * do not fit, FP_ERR_UNSUPPORTED if the geometry needs more on-chip memory
+ * per work-group than the kernels are built for (very narrow cells). */
+fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_size,
+                             double dist_source_center,
+                             double dist_source_detector, int32_t n_views,
+                             const double *view_angles, int32_t n_det,
+                             double det_width, fp_geometry **out);
+
+/* Free the geometry's device tables (synchronises the device).  NULL is a
+ * no-op.  The geometry must not be in use by queued work. */
+fp_status fp_geometry_destroy(fp_geometry *g);
+
+/* Forward projection y = A c (eq. (6)): for every image of the batch, every
+ * view and every cell, the sum over pixels of the CNSF entry times the pixel
+ * coefficient.
+ *   image  device, [batch][ny][nx], read only
+ *   sino   device, [batch][n_views][n_det], overwritten (no accumulation)
+ *   batch  >= 1
+ * The two buffers must not overlap.  Each output is written exactly once by
+ * one thread; results are bitwise reproducible run to run. */
+fp_status fp_forward(const fp_geometry *g, const float *image, float *sino,
+                     int32_t batch, void *stream);
+
+/* Back projection z = A^T y, the exact adjoint of fp_forward (same entries):
+ *   sino   device, [batch][n_views][n_det], read only
+ *   image  device, [batch][ny][nx], overwritten
+ * Gather form: each pixel sums its own entries over all views; no atomics,
+ * bitwise reproducible. */
+fp_status fp_back(const fp_geometry *g, const float *sino, float *image,
+                  int32_t batch, void *stream);
+
+/* One SIRT step (simultaneous iterative reconstruction; the iterative family
+ * the paper targets, Sec. I):
+ *     x <- x + relaxation * C .* A^T( R .* (y - A x) ),
+ *     R = 1 ./ (A 1),  C = 1 ./ (A^T 1),  1/0 read as 0.
+ *   image      device, [batch][ny][nx], the iterate x, updated in place
+ *   sino_meas  device, [batch][n_views][n_det], the data y, read only
+ *   relaxation lambda, finite (0 < lambda < 2 for convergence)
+ *   work       device scratch of batch * n_views * n_det floats, owned by the
+ *              caller; holds R .* (y - A x) on return
+ * R and C are built on the geometry's device by the first call (one forward
+ * and one back projection of ones, then the call waits for them); later
+ * calls reuse them.  No clipping is applied to x. */
+fp_status fp_sirt_step(const fp_geometry *g, float *image,
+                       const float *sino_meas, float relaxation, float *work,
+                       int32_t batch, void *stream);
+
+/* Number of (ray, pixel) pairs with a non-zero entry, counted on the device
+ * with the forward kernel's own enumeration and entry arithmetic; the result
+ * is written to *count on return (the call synchronises `stream`).  Used to
+ * price the work of a projection. */
+fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream);
+
+/* Device bytes held by the geometry: its tables and, once built, the SIRT
+ * weights.  0 for NULL.  Serving code uses it for admission by free memory. */
+size_t fp_geometry_device_bytes(const fp_geometry *g);
+
+/* Text for the last non-OK status returned on the calling thread ("" if
+ * none).  The pointer stays valid until the thread's next fanproj call. */
+const char *fp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FANPROJ_H */

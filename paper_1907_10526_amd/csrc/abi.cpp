@@ -1,0 +1,303 @@
+// The C ABI of libfanproj: argument checks, device selection, batching into
+// kernel launches, the lazily built SIRT weights, and error text.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fanproj_internal.h"
+
+namespace fanproj {
+namespace {
+
+thread_local std::string g_last_error;
+
+// Makes the geometry's device current for the duration of a call and
+// restores the caller's device afterwards.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) {
+        err_ = hipGetDevice(&prev_);
+        if (err_ == hipSuccess && prev_ != dev) {
+            err_ = hipSetDevice(dev);
+            switched_ = err_ == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (switched_) (void)hipSetDevice(prev_);
+    }
+    hipError_t status() const { return err_; }
+
+  private:
+    int prev_ = 0;
+    bool switched_ = false;
+    hipError_t err_ = hipSuccess;
+};
+
+// A pointer is accepted when HIP knows it as device (or managed) memory of
+// the geometry's device.
+fp_status check_device_ptr(const void *p, int dev, const char *what) {
+    if (!p) {
+        set_error(std::string(what) + " is NULL");
+        return FP_ERR_INVALID_ARG;
+    }
+    hipPointerAttribute_t attr{};
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string(what) + " is not device memory");
+        return FP_ERR_INVALID_ARG;
+    }
+    const bool device_mem = attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+    if (!device_mem) {
+        set_error(std::string(what) + " is not device memory");
+        return FP_ERR_INVALID_ARG;
+    }
+    if (attr.type == hipMemoryTypeDevice && attr.device != dev) {
+        set_error(std::string(what) + " lives on device " + std::to_string(attr.device) +
+                  ", the geometry on device " + std::to_string(dev));
+        return FP_ERR_INVALID_ARG;
+    }
+    return FP_OK;
+}
+
+int chunk_for(int remaining, int max_nb) {
+    int nb = 1;
+    while (nb * 2 <= remaining && nb * 2 <= max_nb) nb *= 2;
+    return nb;
+}
+
+int back_max_chunk(const DevGeom &g) { return std::max(back_max_batch(g), 1); }
+
+// Stream-ordered scratch for the padded image copies of the forward walk:
+// one library-owned memory pool per device that keeps its memory between
+// calls, so concurrent calls on different streams get separate buffers and a
+// steady stream of calls does not reach the driver's allocator.
+std::mutex g_pool_mu;
+std::vector<hipMemPool_t> g_pools;
+
+hipError_t device_pool(int dev, hipMemPool_t *out) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1, nullptr);
+    if (!g_pools[dev]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        hipError_t e = hipMemPoolCreate(&pool, &props);
+        if (e != hipSuccess) return e;
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess) return e;
+        g_pools[dev] = pool;
+    }
+    *out = g_pools[dev];
+    return hipSuccess;
+}
+
+// Scratch buffer freed (stream-ordered) when it goes out of scope.
+class Scratch {
+  public:
+    Scratch(int dev, size_t bytes, hipStream_t s) : stream_(s) {
+        hipMemPool_t pool = nullptr;
+        err_ = device_pool(dev, &pool);
+        if (err_ == hipSuccess) err_ = hipMallocFromPoolAsync(&ptr_, bytes, pool, s);
+        if (err_ != hipSuccess) ptr_ = nullptr;
+    }
+    ~Scratch() {
+        if (ptr_) (void)hipFreeAsync(ptr_, stream_);
+    }
+    float *get() const { return static_cast<float *>(ptr_); }
+    hipError_t status() const { return err_; }
+
+  private:
+    void *ptr_ = nullptr;
+    hipStream_t stream_;
+    hipError_t err_ = hipSuccess;
+};
+
+fp_status scratch_error(const char *fn, hipError_t e) {
+    (void)hipGetLastError();
+    set_error(std::string(fn) + ": scratch allocation failed: " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? FP_ERR_OUT_OF_MEMORY : FP_ERR_DEVICE;
+}
+
+fp_status check_call(const fp_geometry *g, int32_t batch, const char *fn) {
+    if (!g) {
+        set_error(std::string(fn) + ": geometry is NULL");
+        return FP_ERR_INVALID_ARG;
+    }
+    if (batch < 1) {
+        set_error(std::string(fn) + ": batch must be >= 1");
+        return FP_ERR_INVALID_ARG;
+    }
+    return FP_OK;
+}
+
+fp_status ensure_weights(fp_geometry *g, hipStream_t stream) {
+    std::lock_guard<std::mutex> lock(g->weights_mu);
+    if (g->weights_ready) return FP_OK;
+    const size_t nr = (size_t)g->nv * g->nd, np = (size_t)g->nx * g->ny;
+    hipError_t e = hipSuccess;
+    if (!g->row_w) e = hipMalloc(&g->row_w, nr * sizeof(float));
+    if (e == hipSuccess && !g->col_w) e = hipMalloc(&g->col_w, np * sizeof(float));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string("fp_sirt_step: allocating the SIRT weights failed: ") +
+                  hipGetErrorString(e));
+        return FP_ERR_OUT_OF_MEMORY;
+    }
+    e = launch_forward(g->dev, FwdMode::kOnes, 1, nullptr, nullptr, g->row_w, nullptr, nullptr,
+                       nullptr, stream);
+    if (e != hipSuccess) return device_error("fp_sirt_step: row sums", e);
+    e = launch_back(g->dev, BackMode::kOnes, 1, nullptr, g->col_w, nullptr, nullptr, 0.0f, stream);
+    if (e != hipSuccess) return device_error("fp_sirt_step: column sums", e);
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error("fp_sirt_step: building the weights", e);
+    g->weight_bytes = (nr + np) * sizeof(float);
+    g->weights_ready = true;
+    return FP_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+fp_status device_error(const char *what, hipError_t e) {
+    (void)hipGetLastError();
+    set_error(std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+    return FP_ERR_DEVICE;
+}
+
+}  // namespace fanproj
+
+using namespace fanproj;
+
+extern "C" const char *fp_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" fp_status fp_forward(const fp_geometry *g, const float *image, float *sino,
+                                int32_t batch, void *stream) {
+    clear_error();
+    fp_status st = check_call(g, batch, "fp_forward");
+    if (st != FP_OK) return st;
+    DeviceGuard guard(g->device);
+    if (guard.status() != hipSuccess) return device_error("fp_forward: hipSetDevice", guard.status());
+    if ((st = check_device_ptr(image, g->device, "fp_forward: image")) != FP_OK) return st;
+    if ((st = check_device_ptr(sino, g->device, "fp_forward: sino")) != FP_OK) return st;
+    const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int max_nb = chunk_for(batch, kMaxBatchChunk);
+    Scratch work(g->device, forward_work_bytes(g->dev, max_nb), s);
+    if (work.status() != hipSuccess) return scratch_error("fp_forward", work.status());
+    for (int b0 = 0; b0 < batch;) {
+        const int nb = chunk_for(batch - b0, kMaxBatchChunk);
+        hipError_t e = launch_forward(g->dev, FwdMode::kPlain, nb, image + b0 * np, work.get(),
+                                      sino + b0 * nr, nullptr, nullptr, nullptr, s);
+        if (e != hipSuccess) return device_error("fp_forward: launch", e);
+        b0 += nb;
+    }
+    return FP_OK;
+}
+
+extern "C" fp_status fp_back(const fp_geometry *g, const float *sino, float *image, int32_t batch,
+                             void *stream) {
+    clear_error();
+    fp_status st = check_call(g, batch, "fp_back");
+    if (st != FP_OK) return st;
+    DeviceGuard guard(g->device);
+    if (guard.status() != hipSuccess) return device_error("fp_back: hipSetDevice", guard.status());
+    if ((st = check_device_ptr(sino, g->device, "fp_back: sino")) != FP_OK) return st;
+    if ((st = check_device_ptr(image, g->device, "fp_back: image")) != FP_OK) return st;
+    const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int max_nb = back_max_chunk(g->dev);
+    const size_t pbytes = back_work_bytes(g->dev, chunk_for(batch, max_nb));
+    Scratch partial(g->device, std::max<size_t>(pbytes, 256), s);
+    if (partial.status() != hipSuccess) return scratch_error("fp_back", partial.status());
+    for (int b0 = 0; b0 < batch;) {
+        const int nb = chunk_for(batch - b0, max_nb);
+        hipError_t e = launch_back(g->dev, BackMode::kPlain, nb, sino + b0 * nr, image + b0 * np,
+                                   pbytes ? partial.get() : nullptr, nullptr, 0.0f, s);
+        if (e != hipSuccess) return device_error("fp_back: launch", e);
+        b0 += nb;
+    }
+    return FP_OK;
+}
+
+extern "C" fp_status fp_sirt_step(const fp_geometry *g_const, float *image, const float *sino_meas,
+                                  float relaxation, float *work, int32_t batch, void *stream) {
+    clear_error();
+    fp_status st = check_call(g_const, batch, "fp_sirt_step");
+    if (st != FP_OK) return st;
+    if (!std::isfinite(relaxation)) {
+        set_error("fp_sirt_step: relaxation must be finite");
+        return FP_ERR_INVALID_ARG;
+    }
+    // The weights are the only state a geometry acquires after creation.
+    fp_geometry *g = const_cast<fp_geometry *>(g_const);
+    DeviceGuard guard(g->device);
+    if (guard.status() != hipSuccess)
+        return device_error("fp_sirt_step: hipSetDevice", guard.status());
+    if ((st = check_device_ptr(image, g->device, "fp_sirt_step: image")) != FP_OK) return st;
+    if ((st = check_device_ptr(sino_meas, g->device, "fp_sirt_step: sino_meas")) != FP_OK) return st;
+    if ((st = check_device_ptr(work, g->device, "fp_sirt_step: work")) != FP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = ensure_weights(g, s)) != FP_OK) return st;
+    const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
+    const int back_nb = back_max_chunk(g->dev);
+    const int max_nb = chunk_for(batch, std::min(kMaxBatchChunk, back_nb));
+    Scratch scratch(g->device, forward_work_bytes(g->dev, max_nb), s);
+    if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step", scratch.status());
+    const size_t pbytes = back_work_bytes(g->dev, max_nb);
+    Scratch partial(g->device, std::max<size_t>(pbytes, 256), s);
+    if (partial.status() != hipSuccess) return scratch_error("fp_sirt_step", partial.status());
+    for (int b0 = 0; b0 < batch;) {
+        const int nb = chunk_for(batch - b0, std::min(kMaxBatchChunk, back_nb));
+        hipError_t e = launch_forward(g->dev, FwdMode::kSirtResidual, nb, image + b0 * np,
+                                      scratch.get(), work + b0 * nr, nullptr, sino_meas + b0 * nr,
+                                      g->row_w, s);
+        if (e != hipSuccess) return device_error("fp_sirt_step: forward launch", e);
+        e = launch_back(g->dev, BackMode::kSirtUpdate, nb, work + b0 * nr, image + b0 * np,
+                        pbytes ? partial.get() : nullptr, g->col_w, relaxation, s);
+        if (e != hipSuccess) return device_error("fp_sirt_step: back launch", e);
+        b0 += nb;
+    }
+    return FP_OK;
+}
+
+extern "C" fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream) {
+    clear_error();
+    fp_status st = check_call(g, 1, "fp_count_nonzero");
+    if (st != FP_OK) return st;
+    if (!count) {
+        set_error("fp_count_nonzero: count is NULL");
+        return FP_ERR_INVALID_ARG;
+    }
+    DeviceGuard guard(g->device);
+    if (guard.status() != hipSuccess)
+        return device_error("fp_count_nonzero: hipSetDevice", guard.status());
+    const size_t nr = (size_t)g->nv * g->nd;
+    int *d_counts = nullptr;
+    hipError_t e = hipMalloc(&d_counts, nr * sizeof(int));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("fp_count_nonzero: allocation failed");
+        return FP_ERR_OUT_OF_MEMORY;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int> h(nr);
+    e = launch_forward(g->dev, FwdMode::kCount, 1, nullptr, nullptr, nullptr, d_counts, nullptr,
+                       nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_counts, nr * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_counts);
+    if (e != hipSuccess) return device_error("fp_count_nonzero", e);
+    int64_t total = 0;
+    for (int c : h) total += c;
+    *count = total;
+    return FP_OK;
+}

@@ -1,0 +1,257 @@
+// Geometry creation: validation and the FP64 per-view / per-ray tables
+// (the "fan geometry" step that precedes every projection, Sec. II-A and
+// eq. (13), (16), (17)), uploaded to the device once.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "fanproj_internal.h"
+
+namespace fanproj {
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool finite_positive(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+}  // namespace fanproj
+
+using namespace fanproj;
+
+extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_size,
+                                        double dist_source_center,
+                                        double dist_source_detector, int32_t n_views,
+                                        const double *view_angles, int32_t n_det,
+                                        double det_width, fp_geometry **out) {
+    clear_error();
+    if (!out) { set_error("fp_geometry_create: out is NULL"); return FP_ERR_INVALID_ARG; }
+    if (!view_angles) { set_error("fp_geometry_create: view_angles is NULL"); return FP_ERR_INVALID_ARG; }
+    if (nx < 1 || ny < 1 || n_views < 1 || n_det < 1) {
+        set_error("fp_geometry_create: nx, ny, n_views and n_det must be >= 1");
+        return FP_ERR_INVALID_ARG;
+    }
+    if (!finite_positive(pixel_size) || !finite_positive(det_width) ||
+        !finite_positive(dist_source_center) || !std::isfinite(dist_source_detector)) {
+        set_error("fp_geometry_create: pixel_size, det_width and the distances must be finite and > 0");
+        return FP_ERR_INVALID_ARG;
+    }
+    if (!(dist_source_detector > dist_source_center)) {
+        set_error("fp_geometry_create: dist_source_detector must exceed dist_source_center");
+        return FP_ERR_INVALID_ARG;
+    }
+    const double half_diag = pixel_size * 0.5 * std::sqrt((double)nx * nx + (double)ny * ny);
+    if (!(dist_source_center > half_diag + pixel_size)) {
+        set_error("fp_geometry_create: the source must lie outside the image "
+                  "(dist_source_center > pixel_size * (sqrt(nx^2+ny^2)/2 + 1))");
+        return FP_ERR_INVALID_ARG;
+    }
+    for (int v = 0; v < n_views; ++v)
+        if (!std::isfinite(view_angles[v])) {
+            set_error("fp_geometry_create: view angle " + std::to_string(v) + " is not finite");
+            return FP_ERR_INVALID_ARG;
+        }
+    if ((int64_t)n_views * n_det > (int64_t)1 << 30 || (int64_t)nx * ny > (int64_t)1 << 30) {
+        set_error("fp_geometry_create: problem too large for 32-bit ray / pixel indices");
+        return FP_ERR_UNSUPPORTED;
+    }
+
+    auto g = std::make_unique<fp_geometry>();
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) return device_error("hipGetDevice", e);
+    g->nx = nx; g->ny = ny; g->nv = n_views; g->nd = n_det;
+    g->pixel = pixel_size; g->dsc = dist_source_center; g->dsd = dist_source_detector;
+    g->tau = det_width;
+    g->angles.assign(view_angles, view_angles + n_views);
+
+    const size_t nr = (size_t)n_views * n_det;
+    const int tiles_x = (nx + kBackTileW - 1) / kBackTileW;
+    const int tiles_y = (ny + kBackTileH - 1) / kBackTileH;
+    const size_t ntiles = (size_t)tiles_x * tiles_y;
+
+    // ---- host tables (FP64 arithmetic) ----
+    std::vector<double> views(2 * (size_t)n_views);
+    std::vector<float> inv_r(nr), ghr(nr), hab(nr), hba(nr), inv2a(nr), wb(nr);
+    std::vector<int32_t> tile_cells(2 * (size_t)n_views * ntiles);
+    const double D = dist_source_detector, tau = det_width, delta = pixel_size;
+    const double c0 = 0.5 * (n_det - 1);
+    int max_cells = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const double cs = std::cos(view_angles[v]), sn = std::sin(view_angles[v]);
+        views[2 * v] = cs;
+        views[2 * v + 1] = sn;
+        // u = (cs, sn) towards the source; e = (sn, -cs) along the detector.
+        for (int m = 0; m < n_det; ++m) {
+            const double s = (m - c0) * tau;
+            const double R = std::sqrt(D * D + s * s);
+            // w_perp = (D e + s u) / R: unit normal of the ray through s.
+            const double wpx = (D * sn + s * cs) / R;
+            const double wpy = (-D * cs + s * sn) / R;
+            const double z1 = delta * std::fabs(wpx), z2 = delta * std::fabs(wpy);
+            const double a = std::min(z1, z2), b = std::max(z1, z2);
+            // eq. (17): tau' = L * (tan_hi - tan_lo) with
+            // tan_(+-) = D (s_(+-) - s) / (D^2 + s s_(+-)), s_(+-) = s +- tau/2.
+            const double gm = 0.5 * tau * D *
+                              (1.0 / (D * D + s * (s + 0.5 * tau)) +
+                               1.0 / (D * D + s * (s - 0.5 * tau)));
+            const size_t r = (size_t)v * n_det + m;
+            inv_r[r] = (float)(1.0 / R);
+            ghr[r] = (float)(gm / (2.0 * R));
+            hab[r] = (float)(0.5 * (a + b));
+            hba[r] = (float)(0.5 * (b - a));
+            inv2a[r] = (float)(0.5 / std::max(a, 1e-30));
+            wb[r] = (float)(delta * delta / (2.0 * b));
+        }
+    }
+    // Largest half effective blur anywhere: tau'/2 = g_m L / 2 with
+    // L <= D_sc D / R_m + (radius of the image) <= D_sc + half_diag + delta.
+    double gmax = 0.0;
+    for (int m = 0; m < n_det; ++m) {
+        const double s = (m - c0) * tau;
+        gmax = std::max(gmax, 0.5 * tau * D *
+                                  (1.0 / (D * D + s * (s + 0.5 * tau)) +
+                                   1.0 / (D * D + s * (s - 0.5 * tau))));
+    }
+    const double hc_max = 0.5 * gmax * (dist_source_center + half_diag + delta);
+    // Cells that any pixel of a back-projection tile can touch.  A non-zero
+    // entry needs the ray through the cell centre to pass within hab + hc of
+    // the pixel centre, i.e. to cross the pixel dilated by hc <= hc_max; so
+    // the ray crosses the tile rectangle dilated by hc_max, whose detector
+    // shadow is spanned by its corners.  One guard cell on each side.
+    const double x0 = -0.5 * (nx - 1) * delta, y0 = -0.5 * (ny - 1) * delta;
+    for (int v = 0; v < n_views; ++v) {
+        const double cs = views[2 * v], sn = views[2 * v + 1];
+        for (int ty = 0; ty < tiles_y; ++ty)
+            for (int tx = 0; tx < tiles_x; ++tx) {
+                const int i0 = tx * kBackTileW, i1 = std::min(nx, i0 + kBackTileW) - 1;
+                const int j0 = ty * kBackTileH, j1 = std::min(ny, j0 + kBackTileH) - 1;
+                const double xs[2] = {x0 + (i0 - 0.5) * delta - hc_max, x0 + (i1 + 0.5) * delta + hc_max};
+                const double ys[2] = {y0 + (j0 - 0.5) * delta - hc_max, y0 + (j1 + 0.5) * delta + hc_max};
+                double smin = INFINITY, smax = -INFINITY;
+                bool in_front = true;
+                for (double x : xs)
+                    for (double y : ys) {
+                        const double depth = dist_source_center - (cs * x + sn * y);
+                        if (!(depth > 0.0)) in_front = false;
+                        const double sh = D * (sn * x - cs * y) / depth;
+                        smin = std::min(smin, sh);
+                        smax = std::max(smax, sh);
+                    }
+                long lo = 0, hi = n_det - 1;
+                if (in_front) {
+                    lo = std::max((long)std::ceil(smin / tau + c0) - 1, 0L);
+                    hi = std::min((long)std::floor(smax / tau + c0) + 1, (long)n_det - 1);
+                }
+                const int cnt = hi >= lo ? (int)(hi - lo + 1) : 0;
+                const size_t t = ((size_t)v * ntiles + (size_t)ty * tiles_x + tx) * 2;
+                tile_cells[t] = cnt ? (int32_t)lo : 0;
+                tile_cells[t + 1] = cnt;
+                max_cells = std::max(max_cells, cnt);
+            }
+    }
+
+    // ---- device block ----
+    const size_t A = 256;
+    size_t off = 0;
+    const size_t off_views = off; off = align_up(off + views.size() * sizeof(double), A);
+    size_t off_rays[6];
+    for (int k = 0; k < 6; ++k) { off_rays[k] = off; off = align_up(off + nr * sizeof(float), A); }
+    const size_t off_tiles = off; off = align_up(off + tile_cells.size() * sizeof(int32_t), A);
+    g->table_bytes = off;
+
+    DevGeom &d = g->dev;
+    d.nx = nx; d.ny = ny; d.nv = n_views; d.nd = n_det;
+    d.tiles_x = tiles_x; d.tiles_y = tiles_y;
+    d.max_cells = max_cells;
+    d.pixel = delta; d.dsc = dist_source_center; d.dsd = D; d.tau = tau;
+    d.half_diag = half_diag + delta;
+    d.back_cap = 0;
+    for (int cap : kBackCaps)
+        if (max_cells <= cap) { d.back_cap = cap; break; }
+    if (d.back_cap == 0) {
+        set_error("fp_geometry_create: a back-projection tile spans " + std::to_string(max_cells) +
+                  " cells, more than the on-chip staging holds (" + std::to_string(kBackMaxCap) +
+                  "; cells too narrow for the pixel size)");
+        return FP_ERR_UNSUPPORTED;
+    }
+    if (back_max_batch(d) < 1) {
+        set_error("fp_geometry_create: a back-projection tile spans " + std::to_string(max_cells) +
+                  " cells, more than the on-chip staging holds");
+        return FP_ERR_UNSUPPORTED;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
+        cus < 1) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    {
+        const long want = ((long)kBackGroupsPerCu * cus + (long)ntiles - 1) / (long)ntiles;
+        long groups = std::max(1L, std::min<long>(want, kBackMaxGroups));
+        while (groups > 1 && n_views / groups < 8) --groups;
+        d.back_groups = (int)groups;
+    }
+    // Per-pixel cell bound of the back projection:
+    //   |s_m - s_k| (1 - delta / (sqrt2 h) - kappa tau / (4D)) < delta P_k / (2h) + kappa tau / 2,
+    //   kappa = 1 / (1 - tau^2 / (16 D^2)).
+    const double kappa = 1.0 / (1.0 - tau * tau / (16.0 * D * D));
+    d.bnd_pix = (float)(delta / std::sqrt(2.0));
+    d.bnd_den = (float)(1.0 - kappa * tau / (4.0 * D));
+    d.bnd_blur = (float)(0.5 * kappa * tau);
+
+    e = hipMalloc(&g->table_block, g->table_bytes);
+    if (e != hipSuccess) {
+        g->table_block = nullptr;
+        (void)hipGetLastError();
+        set_error("fp_geometry_create: hipMalloc of " + std::to_string(g->table_bytes) +
+                  " bytes failed: " + hipGetErrorString(e));
+        return FP_ERR_OUT_OF_MEMORY;
+    }
+    char *base = static_cast<char *>(g->table_block);
+    std::vector<char> host(g->table_bytes, 0);
+    std::memcpy(host.data() + off_views, views.data(), views.size() * sizeof(double));
+    const std::vector<float> *rays[6] = {&inv_r, &ghr, &hab, &hba, &inv2a, &wb};
+    for (int k = 0; k < 6; ++k)
+        std::memcpy(host.data() + off_rays[k], rays[k]->data(), nr * sizeof(float));
+    std::memcpy(host.data() + off_tiles, tile_cells.data(), tile_cells.size() * sizeof(int32_t));
+    e = hipMemcpy(base, host.data(), g->table_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(g->table_block);
+        return device_error("fp_geometry_create: table upload", e);
+    }
+    d.views = reinterpret_cast<const double2 *>(base + off_views);
+    d.inv_r = reinterpret_cast<const float *>(base + off_rays[0]);
+    d.ghr = reinterpret_cast<const float *>(base + off_rays[1]);
+    d.hab = reinterpret_cast<const float *>(base + off_rays[2]);
+    d.hba = reinterpret_cast<const float *>(base + off_rays[3]);
+    d.inv2a = reinterpret_cast<const float *>(base + off_rays[4]);
+    d.wb = reinterpret_cast<const float *>(base + off_rays[5]);
+    d.tile_cells = reinterpret_cast<const int2 *>(base + off_tiles);
+    *out = g.release();
+    return FP_OK;
+}
+
+extern "C" fp_status fp_geometry_destroy(fp_geometry *g) {
+    clear_error();
+    if (!g) return FP_OK;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != g->device) e = hipSetDevice(g->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipError_t f = hipSuccess;
+    if (g->table_block) f = hipFree(g->table_block);
+    if (g->row_w) (void)hipFree(g->row_w);
+    if (g->col_w) (void)hipFree(g->col_w);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    delete g;
+    if (e != hipSuccess) return device_error("fp_geometry_destroy", e);
+    if (f != hipSuccess) return device_error("fp_geometry_destroy: hipFree", f);
+    return FP_OK;
+}
+
+extern "C" size_t fp_geometry_device_bytes(const fp_geometry *g) {
+    if (!g) return 0;
+    return g->table_bytes + g->weight_bytes;
+}

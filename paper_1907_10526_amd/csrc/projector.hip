@@ -1,0 +1,740 @@
+// CNSF forward and back projection kernels for gfx950 (MI355X).
+//
+// Every matrix entry is evaluated on the fly (Sec. V-C: no stored system
+// matrix, no look-up table) as the closed form of eq. (18):
+//
+//     A_{(v,m),k} = delta^2 * M_[a, b, tau'](s'),
+//
+// where a <= b are the two pixel edges projected on the normal of the ray
+// through the centre of cell m (eq. (16)), tau' is the effective blur of
+// eq. (17) at the pixel's depth L along that ray, and s' is the signed
+// distance from the ray to the pixel centre (eq. (13)).
+//
+// The 3-direction box spline is evaluated as the moving average of the
+// 2-direction one over the blur width (the convolution of eq. (9)):
+//
+//     M_[a,b,c](x) = ( T(x + c/2) - T(x - c/2) ) / c,
+//
+// with T the antiderivative of the trapezoid M_[a,b].  T is odd about 1/2 and
+// its positive half, times b, is  Gb(y) = min(y, h+) - max(min(y, h+) - h-, 0)^2 / (2a)
+// (h+ = (a+b)/2, h- = (b-a)/2): a clamp, a subtraction, a square.  No
+// truncated power is differenced, so there is no cancellation for near-zero
+// a (axis-aligned rays) and everything runs in FP32.  FP64 is kept for the
+// per-view fan geometry and for the offset of a pixel centre from a ray, the
+// one quantity that is a small difference of large coordinates.
+//
+// Forward projection is ray-driven: one thread per detector cell walks the
+// rows (or columns) of the image its ray crosses, evaluating the few pixels
+// of each row inside the footprint.  Every output is owned by one thread, so
+// there are no atomics and no cross-thread reductions.  The walk reads
+// zero-padded copies of the image, row-major for rays closer to the y axis and
+// transposed for the others, so the pixels of a row are contiguous for every
+// ray and consecutive rays read consecutive addresses.
+//
+// Back projection is a gather: a work-group owns a 16 x 32 pixel tile, two
+// pixels per thread.  For each view it stages the per-ray constants and the
+// sinogram values of the cells its tile can touch in LDS, then every thread
+// sums its pixels' entries from LDS.  Each pixel is written once.
+//
+// Both kernels sum in FP32 in three levels (within a row / view, over blocks
+// of 32 rows / views, and over blocks) to keep the rounding of 10^3 - 10^4
+// terms well under 1e-6 relative.
+#include "fanproj_internal.h"
+
+namespace fanproj {
+namespace {
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// b times the integral over [0, y] (y >= 0) of the centred, unit-mass
+// trapezoid with projected widths a <= b.
+__device__ __forceinline__ float gb(float y, float hab, float hba, float inv2a) {
+    const float ym = fminf(y, hab);
+    const float v = fmaxf(ym - hba, 0.0f);
+    return fmaf(-(v * inv2a), v, ym);
+}
+
+// (2 b hc) * M_[a, b, 2 hc](sp): the blurred footprint up to per-ray and
+// per-entry scale factors.
+__device__ __forceinline__ float footprint_num(float sp, float hc, float hab, float hba,
+                                               float inv2a) {
+    const float x = fabsf(sp);
+    const float y2 = x - hc;
+    const float g1 = gb(x + hc, hab, hba, inv2a);
+    const float g2 = gb(fabsf(y2), hab, hba, inv2a);
+    return g1 - copysignf(g2, y2);
+}
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o));
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o));
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+constexpr int kSumBlock = 32;
+
+// ---------------------------------------------------------------------------
+// Padded image copies for the forward walk, each with NR = max(nx, ny) rows
+// (rows past the image are zero, so a wave whose rays march along different
+// axes can walk the union of their row ranges):
+//   row copy  [nb][NR][nx + 2 pad]: pixel (i, j) at j * (nx + 2 pad) + pad + i
+//   col copy  [nb][NR][ny + 2 pad]: pixel (i, j) at i * (ny + 2 pad) + pad + j
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pad_rows_kernel(const float *__restrict__ img,
+                                                       float *__restrict__ rows, int nx, int ny,
+                                                       int nrows, int nb) {
+    const int w = nx + 2 * kFwdPad;
+    const size_t per = (size_t)w * nrows;
+    const size_t total = per * nb;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t b = e / per, r = e % per;
+        const int j = (int)(r / w), i = (int)(r % w) - kFwdPad;
+        rows[e] = (i >= 0 && i < nx && j < ny) ? img[b * (size_t)nx * ny + (size_t)j * nx + i] : 0.0f;
+    }
+}
+
+// Tiled transpose through LDS: block (32, 8) handles a 32 x 32 tile of the
+// column copy (32 columns i, 32 padded row positions).
+__global__ __launch_bounds__(256) void pad_cols_kernel(const float *__restrict__ img,
+                                                       float *__restrict__ cols, int nx, int ny,
+                                                       int nrows) {
+    __shared__ float tile[32][33];
+    const int b = blockIdx.z;
+    const int w = ny + 2 * kFwdPad;
+    const int i0 = blockIdx.x * 32;              // copy row (image column) block
+    const int p0 = blockIdx.y * 32;              // padded position block
+    const float *src = img + (size_t)b * nx * ny;
+    float *dst = cols + (size_t)b * nrows * w;
+    // read: rows j = p - pad, columns i (coalesced along i)
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int p = p0 + k, j = p - kFwdPad, i = i0 + (int)threadIdx.x;
+        float val = 0.0f;
+        if (p < w && j >= 0 && j < ny && i < nx) val = src[(size_t)j * nx + i];
+        tile[k][threadIdx.x] = val;
+    }
+    __syncthreads();
+    // write: column copy row i, positions p (coalesced along p)
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int i = i0 + k, p = p0 + (int)threadIdx.x;
+        if (i < nrows && p < w) dst[(size_t)i * w + p] = tile[threadIdx.x][k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection: thread = ray (view blockIdx.y, cell m).
+// ---------------------------------------------------------------------------
+struct RayWalk {
+    double S;          // s' at cross index 0 of the current row (FP64)
+    double zm, zc;     // s' steps along the march and cross axes
+    double izc;        // 1 / zc
+    double hq;         // half-span of the footprint along the cross axis, pixels
+    float zcf;         // zc in FP32
+    float hcr, dhq, dhr;   // half blur at cross index 0 of the row, and its steps
+    float hab, hba, inv2a;
+    int nq;            // pixels along the cross axis
+    int nr;            // pixels along the march axis
+    const float *base; // padded copy, cross index 0 of row 0 (image 0)
+    size_t row_stride; // floats between rows of the copy
+    size_t img_stride; // floats between images of the copy
+};
+
+template <int NB, int T, FwdMode MODE>
+__device__ __forceinline__ void walk_rows(RayWalk &w, int r0, int r1, float (&acc)[NB],
+                                          int &nonzero) {
+    float blk[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) blk[b] = 0.0f;
+    int rows_in_blk = 0;
+    for (int r = r0; r <= r1; ++r) {
+        // first cross index that can be inside the footprint of this row;
+        // clamping keeps the window inside the padded copy (a clamped window
+        // lies in the zero margin)
+        int q_lo = (int)floor(fma(-w.S, w.izc, -w.hq)) + 1;
+        q_lo = min(max(q_lo, -kFwdPad), w.nq + kFwdPad - T);
+        const float sp0 = (float)fma((double)q_lo, w.zc, w.S);
+        const float hc0 = fmaf((float)q_lo, w.dhq, w.hcr);
+        float cv[NB][T];
+        if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
+            const float *p = w.base + (size_t)r * w.row_stride + q_lo;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int t = 0; t < T; ++t) cv[b][t] = p[b * w.img_stride + t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                cv[0][t] = ((unsigned)(q_lo + t) < (unsigned)w.nq && r < w.nr) ? 1.0f : 0.0f;
+        }
+        float row[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) row[b] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const float sp = fmaf((float)t, w.zcf, sp0);
+            const float hc = fmaf((float)t, w.dhq, hc0);
+            const float e = footprint_num(sp, hc, w.hab, w.hba, w.inv2a) * fast_rcp(hc);
+            if constexpr (MODE == FwdMode::kCount) {
+                nonzero += (e != 0.0f && cv[0][t] != 0.0f);
+            } else {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) row[b] = fmaf(e, cv[b][t], row[b]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) blk[b] += row[b];
+        if (++rows_in_blk == kSumBlock) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) { acc[b] += blk[b]; blk[b] = 0.0f; }
+            rows_in_blk = 0;
+        }
+        w.S += w.zm;
+        w.hcr += w.dhr;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] += blk[b];
+}
+
+// Rows whose window is wider than the unrolled variants: same arithmetic,
+// a loop over the window with explicit bounds.
+template <int NB, FwdMode MODE>
+__device__ void walk_rows_wide(RayWalk &w, int T, int r0, int r1, float (&acc)[NB],
+                               int &nonzero) {
+    float blk[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) blk[b] = 0.0f;
+    int rows_in_blk = 0;
+    for (int r = r0; r <= r1; ++r) {
+        const int q_lo = (int)floor(fma(-w.S, w.izc, -w.hq)) + 1;
+        const float sp0 = (float)fma((double)q_lo, w.zc, w.S);
+        const float hc0 = fmaf((float)q_lo, w.dhq, w.hcr);
+        float row[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) row[b] = 0.0f;
+        for (int t = 0; t < T; ++t) {
+            const int q = q_lo + t;
+            if ((unsigned)q >= (unsigned)w.nq || r >= w.nr) continue;
+            const float sp = fmaf((float)t, w.zcf, sp0);
+            const float hc = fmaf((float)t, w.dhq, hc0);
+            const float e = footprint_num(sp, hc, w.hab, w.hba, w.inv2a) * fast_rcp(hc);
+            if constexpr (MODE == FwdMode::kCount) {
+                nonzero += (e != 0.0f);
+            } else if constexpr (MODE == FwdMode::kOnes) {
+                row[0] += e;
+            } else {
+                const float *p = w.base + (size_t)r * w.row_stride + q;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) row[b] = fmaf(e, p[b * w.img_stride], row[b]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) blk[b] += row[b];
+        if (++rows_in_blk == kSumBlock) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) { acc[b] += blk[b]; blk[b] = 0.0f; }
+            rows_in_blk = 0;
+        }
+        w.S += w.zm;
+        w.hcr += w.dhr;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] += blk[b];
+}
+
+template <int NB, FwdMode MODE>
+__global__ __launch_bounds__(kFwdThreads) void forward_kernel(
+    DevGeom G, const float *__restrict__ rows, const float *__restrict__ cols,
+    float *__restrict__ out, int *__restrict__ counts, const float *__restrict__ y_meas,
+    const float *__restrict__ row_w) {
+    const int v = blockIdx.y;
+    const int m_thread = blockIdx.x * kFwdThreads + threadIdx.x;
+    const bool active = m_thread < G.nd;
+    // threads past the last cell walk the last ray (their wave needs them for
+    // the wave-wide reductions) and write nothing
+    const int m = active ? m_thread : G.nd - 1;
+    const size_t ray = (size_t)v * G.nd + m;
+    const size_t nrays = (size_t)G.nv * G.nd;
+
+    // ---- per-ray frame in FP64 (Sec. II-A, eq. (13)) ----
+    const double2 cs = G.views[v];
+    const double c = cs.x, sn = cs.y, D = G.dsd;
+    const double s = (m - 0.5 * (G.nd - 1)) * G.tau;
+    const double R = sqrt(D * D + s * s);
+    const double invR = 1.0 / R;
+    // ray direction w = (-D u + s e) / R, u = (c, sn), e = (sn, -c);
+    // normal w_perp = w rotated by +90 degrees.
+    const double wx = (-D * c + s * sn) * invR;
+    const double wy = (-D * sn - s * c) * invR;
+    const double wpx = -wy, wpy = wx;
+    const double px = G.dsc * c, py = G.dsc * sn;
+    const double x0 = -0.5 * (G.nx - 1) * G.pixel, y0 = -0.5 * (G.ny - 1) * G.pixel;
+    // s'(i, j) and L(i, j) are affine in the pixel indices.
+    const double S00 = wpx * (x0 - px) + wpy * (y0 - py);
+    const double L00 = wx * (x0 - px) + wy * (y0 - py);
+    // March along the image axis closest to the ray; the other ("cross")
+    // axis then advances s' by at least delta / sqrt(2) per pixel.
+    const bool by_rows = fabs(wy) >= fabs(wx);
+    const int nq = by_rows ? G.nx : G.ny, nr = by_rows ? G.ny : G.nx;
+
+    RayWalk w;
+    w.zc = G.pixel * (by_rows ? wpx : wpy);
+    w.zm = G.pixel * (by_rows ? wpy : wpx);
+    const double lc = G.pixel * (by_rows ? wx : wy);
+    const double lm = G.pixel * (by_rows ? wy : wx);
+    w.hab = G.hab[ray];
+    w.hba = G.hba[ray];
+    w.inv2a = G.inv2a[ray];
+    // half effective blur hc = tau'/2 = ghr * R * L, affine in (q, r)
+    const double gR = (double)G.ghr[ray] * R;
+    w.dhq = (float)(gR * lc);
+    w.dhr = (float)(gR * lm);
+    w.zcf = (float)w.zc;
+    w.nq = nq;
+    w.nr = nr;
+    w.row_stride = (size_t)nq + 2 * kFwdPad;
+    w.img_stride = w.row_stride * (size_t)max(G.nx, G.ny);
+    w.base = (by_rows ? rows : cols) + kFwdPad;
+
+    // Support |s'| < hab + hc, with hc bounded by its value at the far side
+    // of the disk containing the image.
+    const double lmax = G.dsc * D * invR + G.half_diag;
+    const double hw = (double)w.hab + gR * lmax;
+    w.izc = 1.0 / w.zc;
+    w.hq = hw * fabs(w.izc);
+    const int T = (int)floor(2.0 * w.hq) + 1;   // pixels per row that can be hit
+    // Rows whose window meets [0, nq): qf(r) = qf0 + r dq is the crossing.
+    const double qf0 = -S00 * w.izc, dq = -w.zm * w.izc;
+    const double q_lo_lim = -w.hq - 1.0, q_hi_lim = nq + w.hq;
+    int r_lo = 0, r_hi = nr - 1;
+    if (fabs(dq) > 1e-12) {
+        double ra = (q_lo_lim - qf0) / dq, rb = (q_hi_lim - qf0) / dq;
+        if (ra > rb) { const double t = ra; ra = rb; rb = t; }
+        ra = fmax(ra, -1.0);
+        rb = fmin(rb, (double)nr);
+        r_lo = max(r_lo, (int)floor(ra));
+        r_hi = min(r_hi, (int)ceil(rb));
+    } else if (qf0 <= q_lo_lim || qf0 >= q_hi_lim) {
+        r_hi = -1;
+    }
+    if (r_hi < r_lo) { r_lo = nr; r_hi = -1; }
+
+    // The whole wave walks the union of its rays' rows with one window width:
+    // control flow stays uniform, and rows or pixels outside a ray's own range
+    // read the zero margin or evaluate to zero.
+    const int Tw = wave_max(T);
+    int r0 = wave_min(r_lo);
+    const int r1 = wave_max(r_hi);
+    r0 = max(r0, 0);
+    w.S = S00 + r0 * w.zm;
+    w.hcr = (float)(gR * (L00 + r0 * lm));
+
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.0f;
+    int nonzero = 0;
+    if (r0 <= r1) {
+        switch (Tw) {
+            case 1:
+            case 2: walk_rows<NB, 2, MODE>(w, r0, r1, acc, nonzero); break;
+            case 3: walk_rows<NB, 3, MODE>(w, r0, r1, acc, nonzero); break;
+            case 4: walk_rows<NB, 4, MODE>(w, r0, r1, acc, nonzero); break;
+            case 5: walk_rows<NB, 5, MODE>(w, r0, r1, acc, nonzero); break;
+            case 6: walk_rows<NB, 6, MODE>(w, r0, r1, acc, nonzero); break;
+            case 7:
+            case 8: walk_rows<NB, 8, MODE>(w, r0, r1, acc, nonzero); break;
+            default: walk_rows_wide<NB, MODE>(w, Tw, r0, r1, acc, nonzero); break;
+        }
+    }
+    if (!active) return;
+    const float wbr = G.wb[ray];
+    if constexpr (MODE == FwdMode::kCount) {
+        counts[ray] = nonzero;
+    } else if constexpr (MODE == FwdMode::kOnes) {
+        const float sum = acc[0] * wbr;
+        out[ray] = sum != 0.0f ? 1.0f / sum : 0.0f;
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float y = acc[b] * wbr;
+            if constexpr (MODE == FwdMode::kPlain) {
+                out[b * nrays + ray] = y;
+            } else {  // kSirtResidual
+                out[b * nrays + ray] = row_w[ray] * (y_meas[b * nrays + ray] - y);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Back projection: work-group = kBackTileW x kBackTileH pixel tile and one
+// contiguous group of views (blockIdx.z of gridDim.z groups).  With one group
+// the kernel finishes the pixels itself; with several it writes per-group
+// partial sums that back_finalize_kernel adds in group order.
+// ---------------------------------------------------------------------------
+template <int NB, int CAP>
+struct BackStage {
+    // per-thread share of one view's cells (prefetched into registers)
+    static constexpr int kPer = (CAP + kBackThreads - 1) / kBackThreads;
+    float invr[kPer], ghr[kPer], hab[kPer], hba[kPer], inv2a[kPer], w[kPer][NB];
+    int cnt;
+};
+
+template <int NB, int CAP>
+struct BackLds {
+    float invr[CAP], ghr[CAP], hab[CAP], hba[CAP], inv2a[CAP], w[NB][CAP];
+};
+
+template <int NB, int CAP, BackMode MODE>
+__device__ __forceinline__ void back_prefetch(const DevGeom &G, const float *__restrict__ sino,
+                                              int v, int tile, int ntiles, size_t nrays,
+                                              BackStage<NB, CAP> &st, int &M0) {
+    const int2 tc = G.tile_cells[(size_t)v * ntiles + tile];
+    M0 = tc.x;
+    st.cnt = tc.y;
+#pragma unroll
+    for (int k = 0; k < BackStage<NB, CAP>::kPer; ++k) {
+        const int idx = (int)threadIdx.x + k * kBackThreads;
+        if (idx < st.cnt) {
+            const size_t r = (size_t)v * G.nd + M0 + idx;
+            st.invr[k] = G.inv_r[r];
+            st.ghr[k] = G.ghr[r];
+            st.hab[k] = G.hab[r];
+            st.hba[k] = G.hba[r];
+            st.inv2a[k] = G.inv2a[r];
+            const float wb = G.wb[r];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                st.w[k][b] = (MODE == BackMode::kOnes ? 1.0f : sino[b * nrays + r]) * wb;
+        }
+    }
+}
+
+template <int NB, int CAP>
+__device__ __forceinline__ void back_store(const BackStage<NB, CAP> &st, BackLds<NB, CAP> &l) {
+#pragma unroll
+    for (int k = 0; k < BackStage<NB, CAP>::kPer; ++k) {
+        const int idx = (int)threadIdx.x + k * kBackThreads;
+        if (idx < st.cnt) {
+            l.invr[idx] = st.invr[k];
+            l.ghr[idx] = st.ghr[k];
+            l.hab[idx] = st.hab[k];
+            l.hba[idx] = st.hba[k];
+            l.inv2a[idx] = st.inv2a[k];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) l.w[b][idx] = st.w[k][b];
+        }
+    }
+}
+
+template <int NB, int CAP, BackMode MODE>
+__global__ __launch_bounds__(kBackThreads) void back_kernel(DevGeom G, const float *__restrict__ sino,
+                                                            float *__restrict__ img,
+                                                            float *__restrict__ partial,
+                                                            const float *__restrict__ col_w,
+                                                            float relaxation) {
+    __shared__ BackLds<NB, CAP> lds[2];
+
+    const int tile = blockIdx.y * G.tiles_x + blockIdx.x;
+    const int ntiles = G.tiles_x * G.tiles_y;
+    const size_t npix = (size_t)G.nx * G.ny;
+    const size_t nrays = (size_t)G.nv * G.nd;
+    const int groups = gridDim.z;
+    const int v_begin = (int)(((long)G.nv * blockIdx.z) / groups);
+    const int v_end = (int)(((long)G.nv * (blockIdx.z + 1)) / groups);
+    constexpr int P = kBackPixPerThread;
+    constexpr int kRowStep = kBackThreads / kBackTileW;
+    const int i = blockIdx.x * kBackTileW + (int)(threadIdx.x % kBackTileW);
+    int jj[P];
+    bool valid[P];
+    double xk[P], yk[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        jj[p] = blockIdx.y * kBackTileH + (int)(threadIdx.x / kBackTileW) + p * kRowStep;
+        valid[p] = i < G.nx && jj[p] < G.ny;
+        xk[p] = (i - 0.5 * (G.nx - 1)) * G.pixel;
+        yk[p] = (jj[p] - 0.5 * (G.ny - 1)) * G.pixel;
+    }
+    const double D = G.dsd, tau = G.tau, c0 = 0.5 * (G.nd - 1);
+    const float Df = (float)D, itau = (float)(1.0 / tau), c0f = (float)c0;
+    const float half_pix = (float)(0.5 * G.pixel);
+    const float guard = (float)(1e-3 * tau);
+
+    float acc[P][NB], blk[P][NB];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) { acc[p][b] = 0.0f; blk[p][b] = 0.0f; }
+    int views_in_blk = 0;
+
+    // software pipeline: view v is computed from lds[v & 1] while view v + 1
+    // is loaded into registers; one barrier per view
+    BackStage<NB, CAP> st;
+    int M0_next = 0;
+    if (v_begin < v_end) {
+        back_prefetch<NB, CAP, MODE>(G, sino, v_begin, tile, ntiles, nrays, st, M0_next);
+        back_store<NB, CAP>(st, lds[v_begin & 1]);
+    }
+    __syncthreads();
+
+    for (int v = v_begin; v < v_end; ++v) {
+        const int M0 = M0_next, cnt = st.cnt;
+        const BackLds<NB, CAP> &l = lds[v & 1];
+        if (v + 1 < v_end) back_prefetch<NB, CAP, MODE>(G, sino, v + 1, tile, ntiles, nrays, st, M0_next);
+
+        if (cnt > 0) {
+            const double2 cs = G.views[v];
+            const float csf = (float)cs.x, snf = (float)cs.y;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (!valid[p]) continue;
+                // ---- pixel in the frame of view v (FP64) ----
+                const double ek = xk[p] * cs.y - yk[p] * cs.x;            // e . k
+                const double h = G.dsc - (xk[p] * cs.x + yk[p] * cs.y);   // D_sc - u . k
+                // Cells with a non-zero entry satisfy |s_m - s_k| < H, where
+                // s_k = D (e.k) / h is the pixel centre's shadow.  From
+                // s' = h (s_k - s_m) / R_m and the support |s'| < hab + hc:
+                // the pixel term hab R / h = delta P(s_m) / (2h) with
+                // P(s) = |D sin + s cos| + |-D cos + s sin| (Lipschitz sqrt 2),
+                // the blur term hc R / h <= kappa tau/2 (1 + |s_m - s_k| / (2D)),
+                // which solved for |s_m - s_k| gives H below.
+                const float hf = (float)h, ekf = (float)ek;
+                const float ih = fast_rcp(hf);
+                const float sk = Df * ekf * ih;
+                const float Pk = fabsf(fmaf(Df, snf, sk * csf)) + fabsf(fmaf(-Df, csf, sk * snf));
+                const float den = fmaf(-G.bnd_pix, ih, G.bnd_den);
+                const float H = fmaf(half_pix * Pk, ih, G.bnd_blur) * fast_rcp(den) * 1.00001f +
+                                fmaf(1e-6f, fabsf(sk), guard);
+                const float fm = fmaf(sk, itau, c0f);
+                const int m_lo = max((int)ceilf(fmaf(-H, itau, fm)), M0);
+                const int m_hi = min((int)floorf(fmaf(H, itau, fm)), M0 + cnt - 1);
+                if (m_lo > m_hi) continue;
+                // s' = (D (e.k) - s_m h) / R_m and R_m L = D h + s_m (e.k):
+                // the numerators at m_lo in FP64, then FP32 steps of one cell.
+                const double s_lo = (m_lo - c0) * tau;
+                const float num0 = (float)(D * ek - s_lo * h);
+                const float ln0 = (float)(D * h + s_lo * ek);
+                const float dnum = (float)(tau * h), dln = (float)(tau * ek);
+                float part[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) part[b] = 0.0f;
+                float t = 0.0f;
+                for (int idx = m_lo - M0; idx <= m_hi - M0; ++idx, t += 1.0f) {
+                    const float sp = fmaf(-t, dnum, num0) * l.invr[idx];
+                    const float hc = fmaf(t, dln, ln0) * l.ghr[idx];
+                    const float e = footprint_num(sp, hc, l.hab[idx], l.hba[idx], l.inv2a[idx]) *
+                                    fast_rcp(hc);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) part[b] = fmaf(e, l.w[b][idx], part[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < NB; ++b) blk[p][b] += part[b];
+            }
+        }
+        if (++views_in_blk == kSumBlock) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) { acc[p][b] += blk[p][b]; blk[p][b] = 0.0f; }
+            views_in_blk = 0;
+        }
+        if (v + 1 < v_end) back_store<NB, CAP>(st, lds[(v + 1) & 1]);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (!valid[p]) continue;
+        const size_t pix = (size_t)jj[p] * G.nx + i;
+        if (groups > 1) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                partial[((size_t)blockIdx.z * NB + b) * npix + pix] = acc[p][b] + blk[p][b];
+            continue;
+        }
+        if constexpr (MODE == BackMode::kOnes) {
+            const float sum = acc[p][0] + blk[p][0];
+            img[pix] = sum != 0.0f ? 1.0f / sum : 0.0f;
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float z = acc[p][b] + blk[p][b];
+                if constexpr (MODE == BackMode::kPlain) {
+                    img[b * npix + pix] = z;
+                } else {  // kSirtUpdate
+                    img[b * npix + pix] += relaxation * col_w[pix] * z;
+                }
+            }
+        }
+    }
+}
+
+// Sum of the view-group partials in group order, then the back kernel's
+// epilogue.
+template <int NB, BackMode MODE>
+__global__ __launch_bounds__(256) void back_finalize_kernel(const float *__restrict__ partial,
+                                                            int groups, size_t npix,
+                                                            float *__restrict__ img,
+                                                            const float *__restrict__ col_w,
+                                                            float relaxation) {
+    for (size_t pix = (size_t)blockIdx.x * blockDim.x + threadIdx.x; pix < npix;
+         pix += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float z = 0.0f;
+            for (int g = 0; g < groups; ++g) z += partial[((size_t)g * NB + b) * npix + pix];
+            if constexpr (MODE == BackMode::kOnes) {
+                img[pix] = z != 0.0f ? 1.0f / z : 0.0f;
+            } else if constexpr (MODE == BackMode::kPlain) {
+                img[b * npix + pix] = z;
+            } else {
+                img[b * npix + pix] += relaxation * col_w[pix] * z;
+            }
+        }
+    }
+}
+
+// ------------------------------- launchers ---------------------------------
+
+template <int NB, FwdMode MODE>
+hipError_t launch_fwd_t(const DevGeom &g, const float *img, float *work, float *out, int *counts,
+                        const float *y_meas, const float *row_w, hipStream_t stream) {
+    const float *rows = nullptr, *cols = nullptr;
+    if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
+        const int nrows = std::max(g.nx, g.ny);
+        float *wr = work;
+        float *wc = work + (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
+        const size_t total = (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
+        const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
+        hipLaunchKernelGGL(pad_rows_kernel, dim3(blocks), dim3(256), 0, stream, img, wr, g.nx, g.ny,
+                           nrows, NB);
+        dim3 tgrid((nrows + 31) / 32, (g.ny + 2 * kFwdPad + 31) / 32, NB);
+        hipLaunchKernelGGL(pad_cols_kernel, tgrid, dim3(32, 8), 0, stream, img, wc, g.nx, g.ny,
+                           nrows);
+        rows = wr;
+        cols = wc;
+    }
+    dim3 grid((g.nd + kFwdThreads - 1) / kFwdThreads, g.nv);
+    hipLaunchKernelGGL((forward_kernel<NB, MODE>), grid, dim3(kFwdThreads), 0, stream, g, rows,
+                       cols, out, counts, y_meas, row_w);
+    return hipGetLastError();
+}
+
+template <FwdMode MODE>
+hipError_t launch_fwd_nb(const DevGeom &g, int nb, const float *img, float *work, float *out,
+                         int *counts, const float *y_meas, const float *row_w,
+                         hipStream_t stream) {
+    switch (nb) {
+        case 1: return launch_fwd_t<1, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        case 2: return launch_fwd_t<2, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        case 4: return launch_fwd_t<4, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        case 8: return launch_fwd_t<8, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NB, int CAP, BackMode MODE>
+hipError_t launch_back_t(const DevGeom &g, const float *sino, float *img, float *partial,
+                         const float *col_w, float relaxation, hipStream_t stream) {
+    if constexpr (2 * (size_t)(kBackRayParams + NB) * CAP * sizeof(float) > kBackLdsLimit) {
+        return hipErrorInvalidValue;  // excluded by back_max_batch
+    }
+    const int groups = partial ? g.back_groups : 1;
+    dim3 grid(g.tiles_x, g.tiles_y, groups);
+    hipLaunchKernelGGL((back_kernel<NB, CAP, MODE>), grid, dim3(kBackThreads), 0, stream, g, sino,
+                       img, partial, col_w, relaxation);
+    if (groups > 1) {
+        const size_t npix = (size_t)g.nx * g.ny;
+        const unsigned blocks = (unsigned)std::min<size_t>((npix + 255) / 256, 4096);
+        hipLaunchKernelGGL((back_finalize_kernel<NB, MODE>), dim3(blocks), dim3(256), 0, stream,
+                           partial, groups, npix, img, col_w, relaxation);
+    }
+    return hipGetLastError();
+}
+
+template <int NB, BackMode MODE>
+hipError_t launch_back_cap(const DevGeom &g, const float *sino, float *img, float *partial,
+                           const float *col_w, float relaxation, hipStream_t stream) {
+    switch (g.back_cap) {
+        case 64: return launch_back_t<NB, 64, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        case 128: return launch_back_t<NB, 128, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        case 256: return launch_back_t<NB, 256, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        case 512: return launch_back_t<NB, 512, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        case 1024: return launch_back_t<NB, 1024, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <BackMode MODE>
+hipError_t launch_back_nb(const DevGeom &g, int nb, const float *sino, float *img, float *partial,
+                          const float *col_w, float relaxation, hipStream_t stream) {
+    switch (nb) {
+        case 1: return launch_back_cap<1, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        case 2: return launch_back_cap<2, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        case 4: return launch_back_cap<4, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        case 8: return launch_back_cap<8, MODE>(g, sino, img, partial, col_w, relaxation, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t forward_work_bytes(const DevGeom &g, int nb) {
+    const size_t nrows = (size_t)std::max(g.nx, g.ny);
+    return (size_t)nb * sizeof(float) * nrows * ((size_t)(g.nx + 2 * kFwdPad) + (g.ny + 2 * kFwdPad));
+}
+
+int back_max_batch(const DevGeom &g) {
+    if (g.back_cap <= 0) return 0;
+    // two LDS buffers of (kBackRayParams + nb) arrays of back_cap floats
+    int nb = kMaxBatchChunk;
+    while (nb > 1 && 2 * (size_t)(kBackRayParams + nb) * g.back_cap * sizeof(float) > kBackLdsLimit)
+        nb /= 2;
+    return 2 * (size_t)(kBackRayParams + nb) * g.back_cap * sizeof(float) <= kBackLdsLimit ? nb : 0;
+}
+
+size_t back_work_bytes(const DevGeom &g, int nb) {
+    return g.back_groups > 1 ? (size_t)g.back_groups * nb * g.nx * g.ny * sizeof(float) : 0;
+}
+
+hipError_t launch_forward(const DevGeom &g, FwdMode mode, int nb, const float *img, float *work,
+                          float *out, int *counts, const float *y_meas, const float *row_w,
+                          hipStream_t stream) {
+    switch (mode) {
+        case FwdMode::kPlain:
+            return launch_fwd_nb<FwdMode::kPlain>(g, nb, img, work, out, counts, y_meas, row_w,
+                                                  stream);
+        case FwdMode::kSirtResidual:
+            return launch_fwd_nb<FwdMode::kSirtResidual>(g, nb, img, work, out, counts, y_meas,
+                                                         row_w, stream);
+        case FwdMode::kOnes:
+            return launch_fwd_t<1, FwdMode::kOnes>(g, img, work, out, counts, y_meas, row_w, stream);
+        case FwdMode::kCount:
+            return launch_fwd_t<1, FwdMode::kCount>(g, img, work, out, counts, y_meas, row_w,
+                                                    stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_back(const DevGeom &g, BackMode mode, int nb, const float *sino, float *img,
+                       float *partial, const float *col_w, float relaxation, hipStream_t stream) {
+    switch (mode) {
+        case BackMode::kPlain:
+            return launch_back_nb<BackMode::kPlain>(g, nb, sino, img, partial, col_w, relaxation,
+                                                    stream);
+        case BackMode::kSirtUpdate:
+            return launch_back_nb<BackMode::kSirtUpdate>(g, nb, sino, img, partial, col_w,
+                                                         relaxation, stream);
+        case BackMode::kOnes:
+            return launch_back_cap<1, BackMode::kOnes>(g, sino, img, partial, col_w, relaxation,
+                                                      stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fanproj

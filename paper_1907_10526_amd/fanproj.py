@@ -1,0 +1,196 @@
+"""ctypes binding of libfanproj (the C ABI in ``include/fanproj.h``).
+
+Argument marshalling only: every step of a projection runs in the HIP
+kernels of the shared library.  Tensors are torch CUDA (HIP) float32 tensors,
+passed by device pointer together with torch's current stream.  If the
+library has not been built, importing this module raises ImportError; there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfanproj.so")
+
+FP_OK = 0
+FP_ERR_INVALID_ARG = 1
+FP_ERR_OUT_OF_MEMORY = 2
+FP_ERR_DEVICE = 3
+FP_ERR_UNSUPPORTED = 4
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python -m paper_1907_10526_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_lib.fp_geometry_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_vp)]
+_lib.fp_geometry_create.restype = ctypes.c_int
+_lib.fp_geometry_destroy.argtypes = [_vp]
+_lib.fp_geometry_destroy.restype = ctypes.c_int
+_lib.fp_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
+_lib.fp_forward.restype = ctypes.c_int
+_lib.fp_back.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
+_lib.fp_back.restype = ctypes.c_int
+_lib.fp_sirt_step.argtypes = [_vp, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32, _vp]
+_lib.fp_sirt_step.restype = ctypes.c_int
+_lib.fp_count_nonzero.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp]
+_lib.fp_count_nonzero.restype = ctypes.c_int
+_lib.fp_geometry_device_bytes.argtypes = [_vp]
+_lib.fp_geometry_device_bytes.restype = ctypes.c_size_t
+_lib.fp_last_error.argtypes = []
+_lib.fp_last_error.restype = ctypes.c_char_p
+
+EXPORTED = ("fp_geometry_create", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_sirt_step",
+            "fp_count_nonzero", "fp_geometry_device_bytes", "fp_last_error")
+
+
+class FanprojError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"fanproj status {status}: {message}")
+        self.status = status
+
+
+def fp_last_error() -> str:
+    return (_lib.fp_last_error() or b"").decode()
+
+
+def _check(status: int):
+    if status != FP_OK:
+        raise FanprojError(status, fp_last_error())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, name, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on a GPU")
+    if shape is not None and tuple(t.shape[-len(shape):]) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., {shape})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# -- the C ABI, one Python function per entry point ---------------------------
+
+def fp_geometry_create(nx, ny, pixel_size, dist_source_center, dist_source_detector,
+                       view_angles, n_det, det_width) -> ctypes.c_void_p:
+    ang = np.ascontiguousarray(np.asarray(view_angles, dtype=np.float64))
+    h = ctypes.c_void_p()
+    _check(_lib.fp_geometry_create(int(nx), int(ny), float(pixel_size), float(dist_source_center),
+                                   float(dist_source_detector), int(ang.size),
+                                   ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   int(n_det), float(det_width), ctypes.byref(h)))
+    return h
+
+
+def fp_geometry_destroy(handle) -> None:
+    _check(_lib.fp_geometry_destroy(handle))
+
+
+def fp_forward(handle, image, sino, batch, stream=None) -> None:
+    _check(_lib.fp_forward(handle, _dev_ptr(image, "image"), _dev_ptr(sino, "sino"), int(batch),
+                           _stream_handle(stream)))
+
+
+def fp_back(handle, sino, image, batch, stream=None) -> None:
+    _check(_lib.fp_back(handle, _dev_ptr(sino, "sino"), _dev_ptr(image, "image"), int(batch),
+                        _stream_handle(stream)))
+
+
+def fp_sirt_step(handle, image, sino_meas, relaxation, work, batch, stream=None) -> None:
+    _check(_lib.fp_sirt_step(handle, _dev_ptr(image, "image"), _dev_ptr(sino_meas, "sino_meas"),
+                             float(relaxation), _dev_ptr(work, "work"), int(batch),
+                             _stream_handle(stream)))
+
+
+def fp_count_nonzero(handle, stream=None) -> int:
+    out = ctypes.c_int64()
+    _check(_lib.fp_count_nonzero(handle, ctypes.byref(out), _stream_handle(stream)))
+    return int(out.value)
+
+
+def fp_geometry_device_bytes(handle) -> int:
+    return int(_lib.fp_geometry_device_bytes(handle))
+
+
+# -- convenience wrapper --------------------------------------------------------
+
+class Geometry:
+    """Owns an ``fp_geometry`` and allocates outputs with torch.
+
+    Images are ``[batch, ny, nx]`` (or ``[ny, nx]``), sinograms
+    ``[batch, n_views, n_det]`` (or ``[n_views, n_det]``), float32 on the
+    geometry's GPU.
+    """
+
+    def __init__(self, nx, ny, pixel, dsc, dsd, angles, n_det, det_width):
+        self.nx, self.ny, self.n_det = int(nx), int(ny), int(n_det)
+        self.angles = np.asarray(angles, dtype=np.float64)
+        self.n_views = int(self.angles.size)
+        self.pixel, self.dsc, self.dsd, self.det_width = float(pixel), float(dsc), float(dsd), float(det_width)
+        self.handle = fp_geometry_create(nx, ny, pixel, dsc, dsd, self.angles, n_det, det_width)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            fp_geometry_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, t, shape, name):
+        if t.dim() == len(shape):
+            return 1
+        if t.dim() != len(shape) + 1:
+            raise ValueError(f"{name} must have shape {shape} or (batch, *{shape})")
+        return t.shape[0]
+
+    def forward(self, image, out=None, stream=None):
+        import torch
+        b = self._batch(image, (self.ny, self.nx), "image")
+        if out is None:
+            shape = (self.n_views, self.n_det) if image.dim() == 2 else (b, self.n_views, self.n_det)
+            out = torch.empty(shape, dtype=torch.float32, device=image.device)
+        fp_forward(self.handle, image, out, b, stream)
+        return out
+
+    def back(self, sino, out=None, stream=None):
+        import torch
+        b = self._batch(sino, (self.n_views, self.n_det), "sino")
+        if out is None:
+            shape = (self.ny, self.nx) if sino.dim() == 2 else (b, self.ny, self.nx)
+            out = torch.empty(shape, dtype=torch.float32, device=sino.device)
+        fp_back(self.handle, sino, out, b, stream)
+        return out
+
+    def sirt_step(self, image, sino_meas, relaxation=1.0, work=None, stream=None):
+        import torch
+        b = self._batch(image, (self.ny, self.nx), "image")
+        if work is None:
+            work = torch.empty_like(sino_meas)
+        fp_sirt_step(self.handle, image, sino_meas, relaxation, work, b, stream)
+        return image
+
+    def count_nonzero(self, stream=None) -> int:
+        return fp_count_nonzero(self.handle, stream)
+
+    def device_bytes(self) -> int:
+        return fp_geometry_device_bytes(self.handle)
