@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-views", type=int, default=360,
                    help="views of the workload the FP64 oracle is timed on")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="run one device-to-device copy of this many MiB before timing, as a "
+                        "known-size reference for hardware byte counters")
     return p.parse_args()
 
 
@@ -89,6 +92,14 @@ def main():
     back = torch.empty((scan.n, scan.n), dtype=torch.float32, device=dev)
     nnz = geom.count_nonzero()
     stream = torch.cuda.current_stream()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         geom.forward(img, out=sino)

@@ -18,6 +18,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every value the kernels handle is finite and the sign of a zero never
+    # matters: lets min/max skip NaN canonicalisation and 0*x+y fold
+    "-fno-honor-nans", "-fno-signed-zeros",
     "-Wall",
 ]
 

@@ -31,7 +31,12 @@ constexpr int kFwdMaxUnrolled = 8;   // widest row window with an unrolled varia
 constexpr int kMaxBatchChunk = 8;
 // Per-ray parameter arrays staged in LDS by the back-projection kernel, in
 // addition to one sinogram weight array per image.
-constexpr int kBackRayParams = 5;
+constexpr int kBackRayParams = 6;
+// Zero-weight cells staged on each side of a tile's cell range, so that a
+// pixel's fixed-width window never leaves the staged arrays.
+constexpr int kBackPad = 8;
+// Widest per-tile window with an unrolled cell loop.
+constexpr int kBackMaxUnrolled = 8;
 // Cell capacities (per view and tile) the back projection is instantiated for;
 // the LDS then holds (kBackRayParams + batch) arrays of that many floats.
 constexpr int kBackCaps[] = {64, 128, 256, 512, 1024};
@@ -56,19 +61,19 @@ struct DevGeom {
     double dsc, dsd;         // source-centre, source-detector distances
     double tau;              // cell width (= pitch)
     double half_diag;        // radius of a disk containing every pixel
-    // Per-pixel cell-range bound of the back projection (see back_kernel):
-    float bnd_pix;           // delta / sqrt(2)
-    float bnd_den;           // 1 - kappa tau / (4 D)
-    float bnd_blur;          // kappa tau / 2
     const double2 *views;    // [nv] (cos t, sin t)
     // Per-ray constants, [nv][nd] each (FP32 roundings of FP64 values):
     const float *inv_r;      // 1 / R_m,  R_m = |q(s_m) - p|
     const float *ghr;        // g_m / (2 R_m): half effective blur per unit of R L
     const float *hab;        // (a + b) / 2, a <= b the projected pixel widths
-    const float *hba;        // (b - a) / 2
-    const float *inv2a;      // 1 / (2 max(a, tiny))
+    const float *ia;         // 1 / max(a, tiny)
+    const float *nhbia;      // -(b - a) / (2 max(a, tiny))
+    const float *ha;         // a / 2
     const float *wb;         // delta^2 / (2 b)
-    const int2 *tile_cells;  // [nv][tiles_y * tiles_x] (first cell, count)
+    // [nv][tiles_y * tiles_x]: first cell M0 and count of the cells the tile
+    // can touch, the window width T every pixel of the tile evaluates, and
+    // (as float bits) the bound H on |s_m - s_k| of its non-zero cells.
+    const int4 *tile_cells;
 };
 
 enum class FwdMode : int { kPlain = 0, kSirtResidual = 1, kOnes = 2, kCount = 3 };

@@ -73,8 +73,8 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
 
     // ---- host tables (FP64 arithmetic) ----
     std::vector<double> views(2 * (size_t)n_views);
-    std::vector<float> inv_r(nr), ghr(nr), hab(nr), hba(nr), inv2a(nr), wb(nr);
-    std::vector<int32_t> tile_cells(2 * (size_t)n_views * ntiles);
+    std::vector<float> inv_r(nr), ghr(nr), hab(nr), ia(nr), nhbia(nr), ha(nr), wb(nr);
+    std::vector<int32_t> tile_cells(4 * (size_t)n_views * ntiles);
     const double D = dist_source_detector, tau = det_width, delta = pixel_size;
     const double c0 = 0.5 * (n_det - 1);
     int max_cells = 0;
@@ -99,9 +99,11 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
             const size_t r = (size_t)v * n_det + m;
             inv_r[r] = (float)(1.0 / R);
             ghr[r] = (float)(gm / (2.0 * R));
+            const double a_safe = std::max(a, 1e-30);
             hab[r] = (float)(0.5 * (a + b));
-            hba[r] = (float)(0.5 * (b - a));
-            inv2a[r] = (float)(0.5 / std::max(a, 1e-30));
+            ia[r] = (float)(1.0 / a_safe);
+            nhbia[r] = (float)(-0.5 * (b - a) / a_safe);
+            ha[r] = (float)(0.5 * a);
             wb[r] = (float)(delta * delta / (2.0 * b));
         }
     }
@@ -120,35 +122,73 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     // the pixel centre, i.e. to cross the pixel dilated by hc <= hc_max; so
     // the ray crosses the tile rectangle dilated by hc_max, whose detector
     // shadow is spanned by its corners.  One guard cell on each side.
+    //
+    // Window of one pixel k: its non-zero cells satisfy |s_m - s_k| < H_k
+    // with s_k = D (e.k) / h_k its centre's shadow.  From s' = h (s_k - s_m) / R_m
+    // and the support |s'| < hab + hc: the pixel term hab R / h equals
+    // delta P(s_m) / (2h) with P(s) = |D sin + s cos| + |-D cos + s sin|
+    // (Lipschitz constant sqrt 2); the blur term hc R / h is at most
+    // kappa tau/2 (1 + |s_m - s_k| / (2D)), kappa = 1 / (1 - tau^2 / (16 D^2)).
+    // Solved for |s_m - s_k|:
+    //   H_k = (delta P(s_k) / (2 h_k) + kappa tau / 2) / (1 - delta / (sqrt2 h_k) - kappa tau / (4D)).
+    // Over a tile P(s_k) is largest at an end of the tile's shadow (P is
+    // convex) and h_k smallest at a corner, which bounds H_k by H_tile; the
+    // window of every pixel of the tile then holds T = floor(2 H / tau) + 1 cells.
+    const double kappa = 1.0 / (1.0 - tau * tau / (16.0 * D * D));
     const double x0 = -0.5 * (nx - 1) * delta, y0 = -0.5 * (ny - 1) * delta;
+    int max_window = 0;
     for (int v = 0; v < n_views; ++v) {
         const double cs = views[2 * v], sn = views[2 * v + 1];
+        auto P = [&](double s) { return std::fabs(D * sn + s * cs) + std::fabs(-D * cs + s * sn); };
         for (int ty = 0; ty < tiles_y; ++ty)
             for (int tx = 0; tx < tiles_x; ++tx) {
                 const int i0 = tx * kBackTileW, i1 = std::min(nx, i0 + kBackTileW) - 1;
                 const int j0 = ty * kBackTileH, j1 = std::min(ny, j0 + kBackTileH) - 1;
-                const double xs[2] = {x0 + (i0 - 0.5) * delta - hc_max, x0 + (i1 + 0.5) * delta + hc_max};
-                const double ys[2] = {y0 + (j0 - 0.5) * delta - hc_max, y0 + (j1 + 0.5) * delta + hc_max};
-                double smin = INFINITY, smax = -INFINITY;
+                const double ex[2] = {x0 + (i0 - 0.5) * delta, x0 + (i1 + 0.5) * delta};
+                const double ey[2] = {y0 + (j0 - 0.5) * delta, y0 + (j1 + 0.5) * delta};
+                double smin = INFINITY, smax = -INFINITY, hmin = INFINITY;
+                double dmin = INFINITY, dmax = -INFINITY;
                 bool in_front = true;
-                for (double x : xs)
-                    for (double y : ys) {
+                for (int cx = 0; cx < 2; ++cx)
+                    for (int cy = 0; cy < 2; ++cy) {
+                        const double x = ex[cx], y = ey[cy];
                         const double depth = dist_source_center - (cs * x + sn * y);
-                        if (!(depth > 0.0)) in_front = false;
                         const double sh = D * (sn * x - cs * y) / depth;
                         smin = std::min(smin, sh);
                         smax = std::max(smax, sh);
+                        hmin = std::min(hmin, depth);
+                        // dilated corner
+                        const double xd = x + (cx ? hc_max : -hc_max), yd = y + (cy ? hc_max : -hc_max);
+                        const double dd = dist_source_center - (cs * xd + sn * yd);
+                        if (!(dd > 0.0)) in_front = false;
+                        const double shd = D * (sn * xd - cs * yd) / dd;
+                        dmin = std::min(dmin, shd);
+                        dmax = std::max(dmax, shd);
                     }
                 long lo = 0, hi = n_det - 1;
                 if (in_front) {
-                    lo = std::max((long)std::ceil(smin / tau + c0) - 1, 0L);
-                    hi = std::min((long)std::floor(smax / tau + c0) + 1, (long)n_det - 1);
+                    lo = std::max((long)std::ceil(dmin / tau + c0) - 1, 0L);
+                    hi = std::min((long)std::floor(dmax / tau + c0) + 1, (long)n_det - 1);
                 }
                 const int cnt = hi >= lo ? (int)(hi - lo + 1) : 0;
-                const size_t t = ((size_t)v * ntiles + (size_t)ty * tiles_x + tx) * 2;
+                const double den = 1.0 - delta / (std::sqrt(2.0) * hmin) - kappa * tau / (4.0 * D);
+                double H = (delta * std::max(P(smin), P(smax)) / (2.0 * hmin) + 0.5 * kappa * tau) / den;
+                // margin for the FP32 shadow and window start computed per pixel
+                H = H * (1.0 + 1e-5) + 1e-3 * tau + 1e-6 * std::max(std::fabs(smin), std::fabs(smax));
+                // (capped far above any staged range; the kernel clamps a window
+                // to the staged cells, which hold every non-zero cell)
+                const double Td = std::floor(2.0 * H / tau) + 1.0;
+                int T = den > 0.0 && Td < (double)(1 << 20) ? (int)Td : (1 << 20);
+                const float Hf = (float)H;
+                int32_t Hbits;
+                std::memcpy(&Hbits, &Hf, sizeof(Hbits));
+                const size_t t = ((size_t)v * ntiles + (size_t)ty * tiles_x + tx) * 4;
                 tile_cells[t] = cnt ? (int32_t)lo : 0;
                 tile_cells[t + 1] = cnt;
+                tile_cells[t + 2] = T;
+                tile_cells[t + 3] = Hbits;
                 max_cells = std::max(max_cells, cnt);
+                max_window = std::max(max_window, T);
             }
     }
 
@@ -156,8 +196,9 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     const size_t A = 256;
     size_t off = 0;
     const size_t off_views = off; off = align_up(off + views.size() * sizeof(double), A);
-    size_t off_rays[6];
-    for (int k = 0; k < 6; ++k) { off_rays[k] = off; off = align_up(off + nr * sizeof(float), A); }
+    constexpr int kRayTables = 7;
+    size_t off_rays[kRayTables];
+    for (int k = 0; k < kRayTables; ++k) { off_rays[k] = off; off = align_up(off + nr * sizeof(float), A); }
     const size_t off_tiles = off; off = align_up(off + tile_cells.size() * sizeof(int32_t), A);
     g->table_bytes = off;
 
@@ -168,8 +209,9 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     d.pixel = delta; d.dsc = dist_source_center; d.dsd = D; d.tau = tau;
     d.half_diag = half_diag + delta;
     d.back_cap = 0;
+    (void)max_window;
     for (int cap : kBackCaps)
-        if (max_cells <= cap) { d.back_cap = cap; break; }
+        if (max_cells + 2 * kBackPad <= cap) { d.back_cap = cap; break; }
     if (d.back_cap == 0) {
         set_error("fp_geometry_create: a back-projection tile spans " + std::to_string(max_cells) +
                   " cells, more than the on-chip staging holds (" + std::to_string(kBackMaxCap) +
@@ -193,14 +235,6 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
         while (groups > 1 && n_views / groups < 8) --groups;
         d.back_groups = (int)groups;
     }
-    // Per-pixel cell bound of the back projection:
-    //   |s_m - s_k| (1 - delta / (sqrt2 h) - kappa tau / (4D)) < delta P_k / (2h) + kappa tau / 2,
-    //   kappa = 1 / (1 - tau^2 / (16 D^2)).
-    const double kappa = 1.0 / (1.0 - tau * tau / (16.0 * D * D));
-    d.bnd_pix = (float)(delta / std::sqrt(2.0));
-    d.bnd_den = (float)(1.0 - kappa * tau / (4.0 * D));
-    d.bnd_blur = (float)(0.5 * kappa * tau);
-
     e = hipMalloc(&g->table_block, g->table_bytes);
     if (e != hipSuccess) {
         g->table_block = nullptr;
@@ -212,8 +246,8 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     char *base = static_cast<char *>(g->table_block);
     std::vector<char> host(g->table_bytes, 0);
     std::memcpy(host.data() + off_views, views.data(), views.size() * sizeof(double));
-    const std::vector<float> *rays[6] = {&inv_r, &ghr, &hab, &hba, &inv2a, &wb};
-    for (int k = 0; k < 6; ++k)
+    const std::vector<float> *rays[kRayTables] = {&inv_r, &ghr, &hab, &ia, &nhbia, &ha, &wb};
+    for (int k = 0; k < kRayTables; ++k)
         std::memcpy(host.data() + off_rays[k], rays[k]->data(), nr * sizeof(float));
     std::memcpy(host.data() + off_tiles, tile_cells.data(), tile_cells.size() * sizeof(int32_t));
     e = hipMemcpy(base, host.data(), g->table_bytes, hipMemcpyHostToDevice);
@@ -225,10 +259,11 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     d.inv_r = reinterpret_cast<const float *>(base + off_rays[0]);
     d.ghr = reinterpret_cast<const float *>(base + off_rays[1]);
     d.hab = reinterpret_cast<const float *>(base + off_rays[2]);
-    d.hba = reinterpret_cast<const float *>(base + off_rays[3]);
-    d.inv2a = reinterpret_cast<const float *>(base + off_rays[4]);
-    d.wb = reinterpret_cast<const float *>(base + off_rays[5]);
-    d.tile_cells = reinterpret_cast<const int2 *>(base + off_tiles);
+    d.ia = reinterpret_cast<const float *>(base + off_rays[3]);
+    d.nhbia = reinterpret_cast<const float *>(base + off_rays[4]);
+    d.ha = reinterpret_cast<const float *>(base + off_rays[5]);
+    d.wb = reinterpret_cast<const float *>(base + off_rays[6]);
+    d.tile_cells = reinterpret_cast<const int4 *>(base + off_tiles);
     *out = g.release();
     return FP_OK;
 }

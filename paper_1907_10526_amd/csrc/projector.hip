@@ -16,10 +16,12 @@
 //     M_[a,b,c](x) = ( T(x + c/2) - T(x - c/2) ) / c,
 //
 // with T the antiderivative of the trapezoid M_[a,b].  T is odd about 1/2 and
-// its positive half, times b, is  Gb(y) = min(y, h+) - max(min(y, h+) - h-, 0)^2 / (2a)
-// (h+ = (a+b)/2, h- = (b-a)/2): a clamp, a subtraction, a square.  No
+// its positive half, times b, is
+//     Gb(y) = m - (a/2) u^2,   m = min(y, h+),   u = clamp((m - h-) / a, 0, 1)
+// (h+ = (a+b)/2, h- = (b-a)/2): a min, one clamped FMA, a square.  No
 // truncated power is differenced, so there is no cancellation for near-zero
-// a (axis-aligned rays) and everything runs in FP32.  FP64 is kept for the
+// a (axis-aligned rays: the rounding of u is then multiplied by a/2) and
+// everything runs in FP32.  FP64 is kept for the
 // per-view fan geometry and for the offset of a pixel centre from a ray, the
 // one quantity that is a small difference of large coordinates.
 //
@@ -36,9 +38,9 @@
 // sinogram values of the cells its tile can touch in LDS, then every thread
 // sums its pixels' entries from LDS.  Each pixel is written once.
 //
-// Both kernels sum in FP32 in three levels (within a row / view, over blocks
-// of 32 rows / views, and over blocks) to keep the rounding of 10^3 - 10^4
-// terms well under 1e-6 relative.
+// Both kernels sum in FP32 in two levels (over blocks of 32 rows / views, and
+// over blocks) to keep the rounding of 10^3 - 10^4 terms well under 1e-6
+// relative.
 #include "fanproj_internal.h"
 
 namespace fanproj {
@@ -46,22 +48,29 @@ namespace {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Per-ray constants of the trapezoid M_[a,b], a <= b.
+struct Trap {
+    float hab;    // (a + b) / 2
+    float ia;     // 1 / a  (a clamped away from 0)
+    float nhbia;  // -(b - a) / (2a)
+    float ha;     // a / 2
+};
+
 // b times the integral over [0, y] (y >= 0) of the centred, unit-mass
-// trapezoid with projected widths a <= b.
-__device__ __forceinline__ float gb(float y, float hab, float hba, float inv2a) {
-    const float ym = fminf(y, hab);
-    const float v = fmaxf(ym - hba, 0.0f);
-    return fmaf(-(v * inv2a), v, ym);
+// trapezoid.  The clamp folds into the FMA's output modifier.
+__device__ __forceinline__ float gb(float y, const Trap &p) {
+    const float m = fminf(y, p.hab);
+    const float u = __builtin_amdgcn_fmed3f(fmaf(m, p.ia, p.nhbia), 0.0f, 1.0f);
+    return fmaf(-p.ha * u, u, m);
 }
 
 // (2 b hc) * M_[a, b, 2 hc](sp): the blurred footprint up to per-ray and
 // per-entry scale factors.
-__device__ __forceinline__ float footprint_num(float sp, float hc, float hab, float hba,
-                                               float inv2a) {
+__device__ __forceinline__ float footprint_num(float sp, float hc, const Trap &p) {
     const float x = fabsf(sp);
     const float y2 = x - hc;
-    const float g1 = gb(x + hc, hab, hba, inv2a);
-    const float g2 = gb(fabsf(y2), hab, hba, inv2a);
+    const float g1 = gb(x + hc, p);
+    const float g2 = gb(fabsf(y2), p);
     return g1 - copysignf(g2, y2);
 }
 
@@ -137,7 +146,7 @@ struct RayWalk {
     double hq;         // half-span of the footprint along the cross axis, pixels
     float zcf;         // zc in FP32
     float hcr, dhq, dhr;   // half blur at cross index 0 of the row, and its steps
-    float hab, hba, inv2a;
+    Trap trap;
     int nq;            // pixels along the cross axis
     int nr;            // pixels along the march axis
     const float *base; // padded copy, cross index 0 of row 0 (image 0)
@@ -148,57 +157,51 @@ struct RayWalk {
 template <int NB, int T, FwdMode MODE>
 __device__ __forceinline__ void walk_rows(RayWalk &w, int r0, int r1, float (&acc)[NB],
                                           int &nonzero) {
-    float blk[NB];
+    constexpr bool kLoad = MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual;
+    const float *rowp = w.base + (size_t)r0 * w.row_stride;
+    for (int rb = r0; rb <= r1; rb += kSumBlock) {
+        const int re = min(rb + kSumBlock - 1, r1);
+        float blk[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) blk[b] = 0.0f;
-    int rows_in_blk = 0;
-    for (int r = r0; r <= r1; ++r) {
-        // first cross index that can be inside the footprint of this row;
-        // clamping keeps the window inside the padded copy (a clamped window
-        // lies in the zero margin)
-        int q_lo = (int)floor(fma(-w.S, w.izc, -w.hq)) + 1;
-        q_lo = min(max(q_lo, -kFwdPad), w.nq + kFwdPad - T);
-        const float sp0 = (float)fma((double)q_lo, w.zc, w.S);
-        const float hc0 = fmaf((float)q_lo, w.dhq, w.hcr);
-        float cv[NB][T];
-        if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
-            const float *p = w.base + (size_t)r * w.row_stride + q_lo;
+        for (int b = 0; b < NB; ++b) blk[b] = 0.0f;
+        for (int r = rb; r <= re; ++r, rowp += w.row_stride) {
+            // first cross index that can be inside the footprint of this row;
+            // clamping keeps the window inside the padded copy (a clamped
+            // window lies in the zero margin)
+            int q_lo = (int)floor(fma(-w.S, w.izc, -w.hq)) + 1;
+            q_lo = min(max(q_lo, -kFwdPad), w.nq + kFwdPad - T);
+            const float sp0 = (float)fma((double)q_lo, w.zc, w.S);
+            const float hc0 = fmaf((float)q_lo, w.dhq, w.hcr);
+            w.S += w.zm;
+            w.hcr += w.dhr;
+            float cv[NB][T];
+            if constexpr (kLoad) {
+                const float *p = rowp + q_lo;
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+                for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int t = 0; t < T; ++t) cv[b][t] = p[b * w.img_stride + t];
-        } else {
-#pragma unroll
-            for (int t = 0; t < T; ++t)
-                cv[0][t] = ((unsigned)(q_lo + t) < (unsigned)w.nq && r < w.nr) ? 1.0f : 0.0f;
-        }
-        float row[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) row[b] = 0.0f;
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const float sp = fmaf((float)t, w.zcf, sp0);
-            const float hc = fmaf((float)t, w.dhq, hc0);
-            const float e = footprint_num(sp, hc, w.hab, w.hba, w.inv2a) * fast_rcp(hc);
-            if constexpr (MODE == FwdMode::kCount) {
-                nonzero += (e != 0.0f && cv[0][t] != 0.0f);
+                    for (int t = 0; t < T; ++t) cv[b][t] = p[b * w.img_stride + t];
             } else {
 #pragma unroll
-                for (int b = 0; b < NB; ++b) row[b] = fmaf(e, cv[b][t], row[b]);
+                for (int t = 0; t < T; ++t)
+                    cv[0][t] = ((unsigned)(q_lo + t) < (unsigned)w.nq && r < w.nr) ? 1.0f : 0.0f;
+            }
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const float sp = fmaf((float)t, w.zcf, sp0);
+                const float hc = fmaf((float)t, w.dhq, hc0);
+                const float e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
+                if constexpr (MODE == FwdMode::kCount) {
+                    nonzero += (e != 0.0f && cv[0][t] != 0.0f);
+                } else {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) blk[b] = fmaf(e, cv[b][t], blk[b]);
+                }
             }
         }
 #pragma unroll
-        for (int b = 0; b < NB; ++b) blk[b] += row[b];
-        if (++rows_in_blk == kSumBlock) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) { acc[b] += blk[b]; blk[b] = 0.0f; }
-            rows_in_blk = 0;
-        }
-        w.S += w.zm;
-        w.hcr += w.dhr;
+        for (int b = 0; b < NB; ++b) acc[b] += blk[b];
     }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] += blk[b];
 }
 
 // Rows whose window is wider than the unrolled variants: same arithmetic,
@@ -206,11 +209,12 @@ __device__ __forceinline__ void walk_rows(RayWalk &w, int r0, int r1, float (&ac
 template <int NB, FwdMode MODE>
 __device__ void walk_rows_wide(RayWalk &w, int T, int r0, int r1, float (&acc)[NB],
                                int &nonzero) {
+    for (int rb = r0; rb <= r1; rb += kSumBlock) {
+    const int re = min(rb + kSumBlock - 1, r1);
     float blk[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) blk[b] = 0.0f;
-    int rows_in_blk = 0;
-    for (int r = r0; r <= r1; ++r) {
+    for (int r = rb; r <= re; ++r) {
         const int q_lo = (int)floor(fma(-w.S, w.izc, -w.hq)) + 1;
         const float sp0 = (float)fma((double)q_lo, w.zc, w.S);
         const float hc0 = fmaf((float)q_lo, w.dhq, w.hcr);
@@ -222,7 +226,7 @@ __device__ void walk_rows_wide(RayWalk &w, int T, int r0, int r1, float (&acc)[N
             if ((unsigned)q >= (unsigned)w.nq || r >= w.nr) continue;
             const float sp = fmaf((float)t, w.zcf, sp0);
             const float hc = fmaf((float)t, w.dhq, hc0);
-            const float e = footprint_num(sp, hc, w.hab, w.hba, w.inv2a) * fast_rcp(hc);
+            const float e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
             if constexpr (MODE == FwdMode::kCount) {
                 nonzero += (e != 0.0f);
             } else if constexpr (MODE == FwdMode::kOnes) {
@@ -235,16 +239,12 @@ __device__ void walk_rows_wide(RayWalk &w, int T, int r0, int r1, float (&acc)[N
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) blk[b] += row[b];
-        if (++rows_in_blk == kSumBlock) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) { acc[b] += blk[b]; blk[b] = 0.0f; }
-            rows_in_blk = 0;
-        }
         w.S += w.zm;
         w.hcr += w.dhr;
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] += blk[b];
+    }
 }
 
 template <int NB, FwdMode MODE>
@@ -287,9 +287,10 @@ __global__ __launch_bounds__(kFwdThreads) void forward_kernel(
     w.zm = G.pixel * (by_rows ? wpy : wpx);
     const double lc = G.pixel * (by_rows ? wx : wy);
     const double lm = G.pixel * (by_rows ? wy : wx);
-    w.hab = G.hab[ray];
-    w.hba = G.hba[ray];
-    w.inv2a = G.inv2a[ray];
+    w.trap.hab = G.hab[ray];
+    w.trap.ia = G.ia[ray];
+    w.trap.nhbia = G.nhbia[ray];
+    w.trap.ha = G.ha[ray];
     // half effective blur hc = tau'/2 = ghr * R * L, affine in (q, r)
     const double gR = (double)G.ghr[ray] * R;
     w.dhq = (float)(gR * lc);
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(kFwdThreads) void forward_kernel(
     // Support |s'| < hab + hc, with hc bounded by its value at the far side
     // of the disk containing the image.
     const double lmax = G.dsc * D * invR + G.half_diag;
-    const double hw = (double)w.hab + gR * lmax;
+    const double hw = (double)w.trap.hab + gR * lmax;
     w.izc = 1.0 / w.zc;
     w.hq = hw * fabs(w.izc);
     const int T = (int)floor(2.0 * w.hq) + 1;   // pixels per row that can be hit
@@ -379,55 +380,104 @@ __global__ __launch_bounds__(kFwdThreads) void forward_kernel(
 // ---------------------------------------------------------------------------
 template <int NB, int CAP>
 struct BackStage {
-    // per-thread share of one view's cells (prefetched into registers)
+    // per-thread share of one view's staged cells (prefetched into registers)
     static constexpr int kPer = (CAP + kBackThreads - 1) / kBackThreads;
-    float invr[kPer], ghr[kPer], hab[kPer], hba[kPer], inv2a[kPer], w[kPer][NB];
-    int cnt;
+    float invr[kPer], ghr[kPer], hab[kPer], ia[kPer], nhbia[kPer], ha[kPer], w[kPer][NB];
+    int4 tc;   // tile entry of the view: M0, cnt, T, H bits
 };
 
 template <int NB, int CAP>
 struct BackLds {
-    float invr[CAP], ghr[CAP], hab[CAP], hba[CAP], inv2a[CAP], w[NB][CAP];
+    float invr[CAP], ghr[CAP], hab[CAP], ia[CAP], nhbia[CAP], ha[CAP], w[NB][CAP];
 };
 
+// Staged cell idx holds cell M0 - kBackPad + idx; the kBackPad cells on either
+// side of [M0, M0 + cnt) get zero weight and harmless constants.
 template <int NB, int CAP, BackMode MODE>
 __device__ __forceinline__ void back_prefetch(const DevGeom &G, const float *__restrict__ sino,
                                               int v, int tile, int ntiles, size_t nrays,
-                                              BackStage<NB, CAP> &st, int &M0) {
-    const int2 tc = G.tile_cells[(size_t)v * ntiles + tile];
-    M0 = tc.x;
-    st.cnt = tc.y;
+                                              BackStage<NB, CAP> &st) {
+    st.tc = G.tile_cells[(size_t)v * ntiles + tile];
+    const int M0 = st.tc.x, cnt = st.tc.y;
 #pragma unroll
     for (int k = 0; k < BackStage<NB, CAP>::kPer; ++k) {
         const int idx = (int)threadIdx.x + k * kBackThreads;
-        if (idx < st.cnt) {
-            const size_t r = (size_t)v * G.nd + M0 + idx;
+        const int c = idx - kBackPad;
+        if (c >= 0 && c < cnt) {
+            const size_t r = (size_t)v * G.nd + M0 + c;
             st.invr[k] = G.inv_r[r];
             st.ghr[k] = G.ghr[r];
             st.hab[k] = G.hab[r];
-            st.hba[k] = G.hba[r];
-            st.inv2a[k] = G.inv2a[r];
+            st.ia[k] = G.ia[r];
+            st.nhbia[k] = G.nhbia[r];
+            st.ha[k] = G.ha[r];
             const float wb = G.wb[r];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
                 st.w[k][b] = (MODE == BackMode::kOnes ? 1.0f : sino[b * nrays + r]) * wb;
+        } else {
+            st.invr[k] = 0.0f;
+            st.ghr[k] = 1.0f;
+            st.hab[k] = 1.0f;
+            st.ia[k] = 1.0f;
+            st.nhbia[k] = 0.0f;
+            st.ha[k] = 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) st.w[k][b] = 0.0f;
         }
     }
 }
 
 template <int NB, int CAP>
 __device__ __forceinline__ void back_store(const BackStage<NB, CAP> &st, BackLds<NB, CAP> &l) {
+    const int n = st.tc.y + 2 * kBackPad;
 #pragma unroll
     for (int k = 0; k < BackStage<NB, CAP>::kPer; ++k) {
         const int idx = (int)threadIdx.x + k * kBackThreads;
-        if (idx < st.cnt) {
+        if (idx < n) {
             l.invr[idx] = st.invr[k];
             l.ghr[idx] = st.ghr[k];
             l.hab[idx] = st.hab[k];
-            l.hba[idx] = st.hba[k];
-            l.inv2a[idx] = st.inv2a[k];
+            l.ia[idx] = st.ia[k];
+            l.nhbia[idx] = st.nhbia[k];
+            l.ha[idx] = st.ha[k];
 #pragma unroll
             for (int b = 0; b < NB; ++b) l.w[b][idx] = st.w[k][b];
+        }
+    }
+}
+
+// Entries of one pixel with cells w0 .. w0 + T - 1 of the staged arrays
+// (cell m = M0 - kBackPad + w0 + t).  num0 and ln0 are the numerators of s'
+// and of R L at the first cell; each further cell steps them by -dnum, +dln.
+template <int NB, int CAP, bool UNROLLED>
+__device__ __forceinline__ void back_window(const BackLds<NB, CAP> &l, int w0, int T, float num0,
+                                            float dnum, float ln0, float dln, float (&part)[NB]) {
+    const float *invr = l.invr + w0;
+    const float *ghr = l.ghr + w0;
+    const float *hab = l.hab + w0;
+    const float *ia = l.ia + w0;
+    const float *nhbia = l.nhbia + w0;
+    const float *ha = l.ha + w0;
+    if constexpr (UNROLLED) {
+#pragma unroll
+        for (int t = 0; t < kBackMaxUnrolled; ++t) {
+            if (t >= T) break;  // T is uniform across the work-group
+            const float sp = fmaf(-(float)t, dnum, num0) * invr[t];
+            const float hc = fmaf((float)t, dln, ln0) * ghr[t];
+            const Trap p{hab[t], ia[t], nhbia[t], ha[t]};
+            const float e = footprint_num(sp, hc, p) * fast_rcp(hc);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) part[b] = fmaf(e, l.w[b][w0 + t], part[b]);
+        }
+    } else {
+        for (int t = 0; t < T; ++t) {
+            const float sp = fmaf(-(float)t, dnum, num0) * invr[t];
+            const float hc = fmaf((float)t, dln, ln0) * ghr[t];
+            const Trap p{hab[t], ia[t], nhbia[t], ha[t]};
+            const float e = footprint_num(sp, hc, p) * fast_rcp(hc);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) part[b] = fmaf(e, l.w[b][w0 + t], part[b]);
         }
     }
 }
@@ -450,20 +500,15 @@ __global__ __launch_bounds__(kBackThreads) void back_kernel(DevGeom G, const flo
     constexpr int P = kBackPixPerThread;
     constexpr int kRowStep = kBackThreads / kBackTileW;
     const int i = blockIdx.x * kBackTileW + (int)(threadIdx.x % kBackTileW);
-    int jj[P];
+    const int j0 = blockIdx.y * kBackTileH + (int)(threadIdx.x / kBackTileW);
     bool valid[P];
-    double xk[P], yk[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        jj[p] = blockIdx.y * kBackTileH + (int)(threadIdx.x / kBackTileW) + p * kRowStep;
-        valid[p] = i < G.nx && jj[p] < G.ny;
-        xk[p] = (i - 0.5 * (G.nx - 1)) * G.pixel;
-        yk[p] = (jj[p] - 0.5 * (G.ny - 1)) * G.pixel;
-    }
+    for (int p = 0; p < P; ++p) valid[p] = i < G.nx && j0 + p * kRowStep < G.ny;
+    const double xk = (i - 0.5 * (G.nx - 1)) * G.pixel;
+    const double yk0 = (j0 - 0.5 * (G.ny - 1)) * G.pixel;
+    const double ystep = kRowStep * G.pixel;
     const double D = G.dsd, tau = G.tau, c0 = 0.5 * (G.nd - 1);
-    const float Df = (float)D, itau = (float)(1.0 / tau), c0f = (float)c0;
-    const float half_pix = (float)(0.5 * G.pixel);
-    const float guard = (float)(1e-3 * tau);
+    const float Df = (float)D, tauf = (float)tau, itau = (float)(1.0 / tau);
 
     float acc[P][NB], blk[P][NB];
 #pragma unroll
@@ -475,63 +520,47 @@ __global__ __launch_bounds__(kBackThreads) void back_kernel(DevGeom G, const flo
     // software pipeline: view v is computed from lds[v & 1] while view v + 1
     // is loaded into registers; one barrier per view
     BackStage<NB, CAP> st;
-    int M0_next = 0;
     if (v_begin < v_end) {
-        back_prefetch<NB, CAP, MODE>(G, sino, v_begin, tile, ntiles, nrays, st, M0_next);
+        back_prefetch<NB, CAP, MODE>(G, sino, v_begin, tile, ntiles, nrays, st);
         back_store<NB, CAP>(st, lds[v_begin & 1]);
     }
     __syncthreads();
 
     for (int v = v_begin; v < v_end; ++v) {
-        const int M0 = M0_next, cnt = st.cnt;
+        const int4 tc = st.tc;
+        const int M0 = tc.x, cnt = tc.y, T = tc.z;
+        const float H = __int_as_float(tc.w);
         const BackLds<NB, CAP> &l = lds[v & 1];
-        if (v + 1 < v_end) back_prefetch<NB, CAP, MODE>(G, sino, v + 1, tile, ntiles, nrays, st, M0_next);
+        if (v + 1 < v_end) back_prefetch<NB, CAP, MODE>(G, sino, v + 1, tile, ntiles, nrays, st);
 
         if (cnt > 0) {
             const double2 cs = G.views[v];
-            const float csf = (float)cs.x, snf = (float)cs.y;
+            double ek = xk * cs.y - yk0 * cs.x;             // e . k
+            double h = G.dsc - (xk * cs.x + yk0 * cs.y);    // D_sc - u . k
+            const double dek = -ystep * cs.x, dh = -ystep * cs.y;
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (!valid[p]) continue;
-                // ---- pixel in the frame of view v (FP64) ----
-                const double ek = xk[p] * cs.y - yk[p] * cs.x;            // e . k
-                const double h = G.dsc - (xk[p] * cs.x + yk[p] * cs.y);   // D_sc - u . k
-                // Cells with a non-zero entry satisfy |s_m - s_k| < H, where
-                // s_k = D (e.k) / h is the pixel centre's shadow.  From
-                // s' = h (s_k - s_m) / R_m and the support |s'| < hab + hc:
-                // the pixel term hab R / h = delta P(s_m) / (2h) with
-                // P(s) = |D sin + s cos| + |-D cos + s sin| (Lipschitz sqrt 2),
-                // the blur term hc R / h <= kappa tau/2 (1 + |s_m - s_k| / (2D)),
-                // which solved for |s_m - s_k| gives H below.
+            for (int p = 0; p < P; ++p, ek += dek, h += dh) {
+                // the pixel's window: m_lo = ceil((s_k - H) / tau + c0) with
+                // s_k = D (e.k) / h, shifted (never past a non-zero cell) so
+                // that it stays inside the staged cells
                 const float hf = (float)h, ekf = (float)ek;
-                const float ih = fast_rcp(hf);
-                const float sk = Df * ekf * ih;
-                const float Pk = fabsf(fmaf(Df, snf, sk * csf)) + fabsf(fmaf(-Df, csf, sk * snf));
-                const float den = fmaf(-G.bnd_pix, ih, G.bnd_den);
-                const float H = fmaf(half_pix * Pk, ih, G.bnd_blur) * fast_rcp(den) * 1.00001f +
-                                fmaf(1e-6f, fabsf(sk), guard);
-                const float fm = fmaf(sk, itau, c0f);
-                const int m_lo = max((int)ceilf(fmaf(-H, itau, fm)), M0);
-                const int m_hi = min((int)floorf(fmaf(H, itau, fm)), M0 + cnt - 1);
-                if (m_lo > m_hi) continue;
-                // s' = (D (e.k) - s_m h) / R_m and R_m L = D h + s_m (e.k):
-                // the numerators at m_lo in FP64, then FP32 steps of one cell.
-                const double s_lo = (m_lo - c0) * tau;
-                const float num0 = (float)(D * ek - s_lo * h);
-                const float ln0 = (float)(D * h + s_lo * ek);
-                const float dnum = (float)(tau * h), dln = (float)(tau * ek);
+                const float sk = Df * ekf * fast_rcp(hf);
+                const int m_lo = (int)ceilf(fmaf(sk - H, itau, (float)c0));
+                const int w0 = min(max(m_lo - M0 + kBackPad, 0), cnt + 2 * kBackPad - min(T, cnt + 2 * kBackPad));
+                const int m_first = M0 - kBackPad + w0;
+                // s' = (D (e.k) - s_m h) / R_m and R_m L = D h + s_m (e.k) at the
+                // window's first cell in FP64, then FP32 steps of one cell
+                const double s_first = (m_first - c0) * tau;
+                const float num0 = (float)(D * ek - s_first * h);
+                const float ln0 = fmaf((float)s_first, ekf, Df * hf);
+                const float dnum = tauf * hf, dln = tauf * ekf;
                 float part[NB];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) part[b] = 0.0f;
-                float t = 0.0f;
-                for (int idx = m_lo - M0; idx <= m_hi - M0; ++idx, t += 1.0f) {
-                    const float sp = fmaf(-t, dnum, num0) * l.invr[idx];
-                    const float hc = fmaf(t, dln, ln0) * l.ghr[idx];
-                    const float e = footprint_num(sp, hc, l.hab[idx], l.hba[idx], l.inv2a[idx]) *
-                                    fast_rcp(hc);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) part[b] = fmaf(e, l.w[b][idx], part[b]);
-                }
+                if (T <= kBackMaxUnrolled)
+                    back_window<NB, CAP, true>(l, w0, T, num0, dnum, ln0, dln, part);
+                else
+                    back_window<NB, CAP, false>(l, w0, min(T, cnt + 2 * kBackPad), num0, dnum, ln0, dln, part);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) blk[p][b] += part[b];
             }
@@ -550,7 +579,7 @@ __global__ __launch_bounds__(kBackThreads) void back_kernel(DevGeom G, const flo
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (!valid[p]) continue;
-        const size_t pix = (size_t)jj[p] * G.nx + i;
+        const size_t pix = (size_t)(j0 + p * kRowStep) * G.nx + i;
         if (groups > 1) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
