@@ -112,6 +112,18 @@ fp_status fp_forward(const fp_geometry *g, const float *image, float *sino,
 fp_status fp_back(const fp_geometry *g, const float *sino, float *image,
                   int32_t batch, void *stream);
 
+/* FP64 instantiations of fp_forward and fp_back: the same kernels, entry
+ * arithmetic and accumulation in double precision, with the per-ray
+ * constants in double precision (built on the device by the first FP64 call,
+ * which synchronises).  Layouts, ownership and errors as for the FP32 calls;
+ * FP_ERR_UNSUPPORTED if the back projection's per-tile cell staging does not
+ * fit on chip in FP64.  Meant for checks that need more than FP32 (finite
+ * differences, adjoint identities), not for throughput. */
+fp_status fp_forward_f64(const fp_geometry *g, const double *image, double *sino,
+                         int32_t batch, void *stream);
+fp_status fp_back_f64(const fp_geometry *g, const double *sino, double *image,
+                      int32_t batch, void *stream);
+
 /* One SIRT step (simultaneous iterative reconstruction; the iterative family
  * the paper targets, Sec. I):
  *     x <- x + relaxation * C .* A^T( R .* (y - A x) ),
@@ -128,14 +140,39 @@ fp_status fp_sirt_step(const fp_geometry *g, float *image,
                        const float *sino_meas, float relaxation, float *work,
                        int32_t batch, void *stream);
 
+/* Build the SIRT weights R = 1 ./ (A 1) and C = 1 ./ (A^T 1) of a geometry
+ * now (fp_sirt_step and fp_sirt_step_multi otherwise build them on first
+ * use).  Synchronises `stream` the first time; a no-op afterwards. */
+fp_status fp_sirt_prepare(const fp_geometry *g, void *stream);
+
+/* One job of a grouped SIRT step: a geometry and the job's device buffers
+ * (batch 1).  Buffers of different jobs must not overlap. */
+typedef struct {
+    const fp_geometry *geometry;
+    float *image;            /* [ny][nx], the iterate, updated in place      */
+    const float *sino_meas;  /* [n_views][n_det], the data                   */
+    float *work;             /* [n_views][n_det] scratch; R .* (y - A x) on return */
+    float relaxation;        /* finite                                        */
+} fp_sirt_job;
+
+/* One SIRT step for each of n_jobs jobs whose geometries (image size, views,
+ * detector cells, distances) may all differ, batched into grouped launches:
+ * one launch per phase (padded copies, forward residual, back update) covers
+ * up to 12 jobs, every work-group finding its job from the launch's job
+ * table.  This is the execution step of continuous batching: a serving loop
+ * admits and retires jobs between calls.  The result for each job is that of
+ * fp_sirt_step on it alone, up to the order of FP32 summation over view
+ * groups.  All geometries must live on one device.  n_jobs == 0 is a no-op. */
+fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs, void *stream);
+
 /* Number of (ray, pixel) pairs with a non-zero entry, counted on the device
  * with the forward kernel's own enumeration and entry arithmetic; the result
  * is written to *count on return (the call synchronises `stream`).  Used to
  * price the work of a projection. */
 fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream);
 
-/* Device bytes held by the geometry: its tables and, once built, the SIRT
- * weights.  0 for NULL.  Serving code uses it for admission by free memory. */
+/* Device bytes held by the geometry: its tables and, once built, the FP64
+ * tables and the SIRT weights.  0 for NULL.  Serving code uses it for admission by free memory. */
 size_t fp_geometry_device_bytes(const fp_geometry *g);
 
 /* Text for the last non-OK status returned on the calling thread ("" if

@@ -68,7 +68,7 @@ int chunk_for(int remaining, int max_nb) {
     return nb;
 }
 
-int back_max_chunk(const DevGeom &g) { return std::max(back_max_batch(g), 1); }
+int back_max_chunk(const DevGeom &g) { return std::max(back_max_batch<float>(g), 1); }
 
 // Stream-ordered scratch for the padded image copies of the forward walk:
 // one library-owned memory pool per device that keeps its memory between
@@ -111,6 +111,7 @@ class Scratch {
         if (ptr_) (void)hipFreeAsync(ptr_, stream_);
     }
     float *get() const { return static_cast<float *>(ptr_); }
+    void *raw() const { return ptr_; }
     hipError_t status() const { return err_; }
 
   private:
@@ -150,10 +151,11 @@ fp_status ensure_weights(fp_geometry *g, hipStream_t stream) {
                   hipGetErrorString(e));
         return FP_ERR_OUT_OF_MEMORY;
     }
-    e = launch_forward(g->dev, FwdMode::kOnes, 1, nullptr, nullptr, g->row_w, nullptr, nullptr,
-                       nullptr, stream);
+    e = launch_forward<float>(g->dev, FwdMode::kOnes, 1, nullptr, nullptr, g->row_w, nullptr,
+                              nullptr, nullptr, stream);
     if (e != hipSuccess) return device_error("fp_sirt_step: row sums", e);
-    e = launch_back(g->dev, BackMode::kOnes, 1, nullptr, g->col_w, nullptr, nullptr, 0.0f, stream);
+    e = launch_back<float>(g->dev, BackMode::kOnes, 1, nullptr, g->col_w, nullptr, nullptr, 0.0f,
+                           stream);
     if (e != hipSuccess) return device_error("fp_sirt_step: column sums", e);
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return device_error("fp_sirt_step: building the weights", e);
@@ -179,53 +181,97 @@ using namespace fanproj;
 
 extern "C" const char *fp_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" fp_status fp_forward(const fp_geometry *g, const float *image, float *sino,
-                                int32_t batch, void *stream) {
+namespace fanproj {
+namespace {
+
+template <typename Real>
+fp_status forward_impl(const fp_geometry *gc, const Real *image, Real *sino, int32_t batch,
+                       void *stream, const char *fn) {
     clear_error();
-    fp_status st = check_call(g, batch, "fp_forward");
+    fp_status st = check_call(gc, batch, fn);
     if (st != FP_OK) return st;
+    fp_geometry *g = const_cast<fp_geometry *>(gc);
     DeviceGuard guard(g->device);
-    if (guard.status() != hipSuccess) return device_error("fp_forward: hipSetDevice", guard.status());
-    if ((st = check_device_ptr(image, g->device, "fp_forward: image")) != FP_OK) return st;
-    if ((st = check_device_ptr(sino, g->device, "fp_forward: sino")) != FP_OK) return st;
+    if (guard.status() != hipSuccess) return device_error(fn, guard.status());
+    if ((st = check_device_ptr(image, g->device, "image")) != FP_OK) return st;
+    if ((st = check_device_ptr(sino, g->device, "sino")) != FP_OK) return st;
+    if constexpr (sizeof(Real) == sizeof(double)) {
+        if ((st = ensure_f64_tables(g)) != FP_OK) return st;
+    }
     const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int max_nb = chunk_for(batch, kMaxBatchChunk);
-    Scratch work(g->device, forward_work_bytes(g->dev, max_nb), s);
-    if (work.status() != hipSuccess) return scratch_error("fp_forward", work.status());
+    Scratch work(g->device, forward_work_bytes<Real>(g->dev, max_nb), s);
+    if (work.status() != hipSuccess) return scratch_error(fn, work.status());
     for (int b0 = 0; b0 < batch;) {
         const int nb = chunk_for(batch - b0, kMaxBatchChunk);
-        hipError_t e = launch_forward(g->dev, FwdMode::kPlain, nb, image + b0 * np, work.get(),
-                                      sino + b0 * nr, nullptr, nullptr, nullptr, s);
-        if (e != hipSuccess) return device_error("fp_forward: launch", e);
+        hipError_t e = launch_forward<Real>(g->dev, FwdMode::kPlain, nb, image + b0 * np,
+                                            reinterpret_cast<Real *>(work.get()), sino + b0 * nr,
+                                            nullptr, nullptr, nullptr, s);
+        if (e != hipSuccess) return device_error(fn, e);
         b0 += nb;
     }
     return FP_OK;
 }
 
-extern "C" fp_status fp_back(const fp_geometry *g, const float *sino, float *image, int32_t batch,
-                             void *stream) {
+template <typename Real>
+fp_status back_impl(const fp_geometry *gc, const Real *sino, Real *image, int32_t batch,
+                    void *stream, const char *fn) {
     clear_error();
-    fp_status st = check_call(g, batch, "fp_back");
+    fp_status st = check_call(gc, batch, fn);
     if (st != FP_OK) return st;
+    fp_geometry *g = const_cast<fp_geometry *>(gc);
     DeviceGuard guard(g->device);
-    if (guard.status() != hipSuccess) return device_error("fp_back: hipSetDevice", guard.status());
-    if ((st = check_device_ptr(sino, g->device, "fp_back: sino")) != FP_OK) return st;
-    if ((st = check_device_ptr(image, g->device, "fp_back: image")) != FP_OK) return st;
+    if (guard.status() != hipSuccess) return device_error(fn, guard.status());
+    if ((st = check_device_ptr(sino, g->device, "sino")) != FP_OK) return st;
+    if ((st = check_device_ptr(image, g->device, "image")) != FP_OK) return st;
+    if constexpr (sizeof(Real) == sizeof(double)) {
+        if ((st = ensure_f64_tables(g)) != FP_OK) return st;
+    }
+    const int max_nb = back_max_batch<Real>(g->dev);
+    if (max_nb < 1) {
+        set_error(std::string(fn) + ": the geometry's cell ranges do not fit the on-chip staging "
+                                    "in this precision");
+        return FP_ERR_UNSUPPORTED;
+    }
     const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int max_nb = back_max_chunk(g->dev);
-    const size_t pbytes = back_work_bytes(g->dev, chunk_for(batch, max_nb));
+    const size_t pbytes = back_work_bytes<Real>(g->dev, chunk_for(batch, max_nb));
     Scratch partial(g->device, std::max<size_t>(pbytes, 256), s);
-    if (partial.status() != hipSuccess) return scratch_error("fp_back", partial.status());
+    if (partial.status() != hipSuccess) return scratch_error(fn, partial.status());
     for (int b0 = 0; b0 < batch;) {
         const int nb = chunk_for(batch - b0, max_nb);
-        hipError_t e = launch_back(g->dev, BackMode::kPlain, nb, sino + b0 * nr, image + b0 * np,
-                                   pbytes ? partial.get() : nullptr, nullptr, 0.0f, s);
-        if (e != hipSuccess) return device_error("fp_back: launch", e);
+        hipError_t e = launch_back<Real>(g->dev, BackMode::kPlain, nb, sino + b0 * nr,
+                                         image + b0 * np,
+                                         pbytes ? reinterpret_cast<Real *>(partial.get()) : nullptr,
+                                         nullptr, Real(0), s);
+        if (e != hipSuccess) return device_error(fn, e);
         b0 += nb;
     }
     return FP_OK;
+}
+
+}  // namespace
+}  // namespace fanproj
+
+extern "C" fp_status fp_forward(const fp_geometry *g, const float *image, float *sino,
+                                int32_t batch, void *stream) {
+    return forward_impl<float>(g, image, sino, batch, stream, "fp_forward");
+}
+
+extern "C" fp_status fp_back(const fp_geometry *g, const float *sino, float *image, int32_t batch,
+                             void *stream) {
+    return back_impl<float>(g, sino, image, batch, stream, "fp_back");
+}
+
+extern "C" fp_status fp_forward_f64(const fp_geometry *g, const double *image, double *sino,
+                                    int32_t batch, void *stream) {
+    return forward_impl<double>(g, image, sino, batch, stream, "fp_forward_f64");
+}
+
+extern "C" fp_status fp_back_f64(const fp_geometry *g, const double *sino, double *image,
+                                 int32_t batch, void *stream) {
+    return back_impl<double>(g, sino, image, batch, stream, "fp_back_f64");
 }
 
 extern "C" fp_status fp_sirt_step(const fp_geometry *g_const, float *image, const float *sino_meas,
@@ -250,18 +296,18 @@ extern "C" fp_status fp_sirt_step(const fp_geometry *g_const, float *image, cons
     const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
     const int back_nb = back_max_chunk(g->dev);
     const int max_nb = chunk_for(batch, std::min(kMaxBatchChunk, back_nb));
-    Scratch scratch(g->device, forward_work_bytes(g->dev, max_nb), s);
+    Scratch scratch(g->device, forward_work_bytes<float>(g->dev, max_nb), s);
     if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step", scratch.status());
-    const size_t pbytes = back_work_bytes(g->dev, max_nb);
+    const size_t pbytes = back_work_bytes<float>(g->dev, max_nb);
     Scratch partial(g->device, std::max<size_t>(pbytes, 256), s);
     if (partial.status() != hipSuccess) return scratch_error("fp_sirt_step", partial.status());
     for (int b0 = 0; b0 < batch;) {
         const int nb = chunk_for(batch - b0, std::min(kMaxBatchChunk, back_nb));
-        hipError_t e = launch_forward(g->dev, FwdMode::kSirtResidual, nb, image + b0 * np,
+        hipError_t e = launch_forward<float>(g->dev, FwdMode::kSirtResidual, nb, image + b0 * np,
                                       scratch.get(), work + b0 * nr, nullptr, sino_meas + b0 * nr,
                                       g->row_w, s);
         if (e != hipSuccess) return device_error("fp_sirt_step: forward launch", e);
-        e = launch_back(g->dev, BackMode::kSirtUpdate, nb, work + b0 * nr, image + b0 * np,
+        e = launch_back<float>(g->dev, BackMode::kSirtUpdate, nb, work + b0 * nr, image + b0 * np,
                         pbytes ? partial.get() : nullptr, g->col_w, relaxation, s);
         if (e != hipSuccess) return device_error("fp_sirt_step: back launch", e);
         b0 += nb;
@@ -290,8 +336,8 @@ extern "C" fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<int> h(nr);
-    e = launch_forward(g->dev, FwdMode::kCount, 1, nullptr, nullptr, nullptr, d_counts, nullptr,
-                       nullptr, s);
+    e = launch_forward<float>(g->dev, FwdMode::kCount, 1, nullptr, nullptr, nullptr, d_counts,
+                              nullptr, nullptr, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_counts, nr * sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d_counts);
@@ -299,5 +345,90 @@ extern "C" fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void
     int64_t total = 0;
     for (int c : h) total += c;
     *count = total;
+    return FP_OK;
+}
+
+extern "C" fp_status fp_sirt_prepare(const fp_geometry *gc, void *stream) {
+    clear_error();
+    fp_status st = check_call(gc, 1, "fp_sirt_prepare");
+    if (st != FP_OK) return st;
+    fp_geometry *g = const_cast<fp_geometry *>(gc);
+    DeviceGuard guard(g->device);
+    if (guard.status() != hipSuccess) return device_error("fp_sirt_prepare", guard.status());
+    return ensure_weights(g, static_cast<hipStream_t>(stream));
+}
+
+extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs, void *stream) {
+    clear_error();
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) {
+        set_error("fp_sirt_step_multi: jobs is NULL or n_jobs < 0");
+        return FP_ERR_INVALID_ARG;
+    }
+    if (n_jobs == 0) return FP_OK;
+    if (!jobs[0].geometry) {
+        set_error("fp_sirt_step_multi: job 0 has no geometry");
+        return FP_ERR_INVALID_ARG;
+    }
+    const int dev = jobs[0].geometry->device;
+    DeviceGuard guard(dev);
+    if (guard.status() != hipSuccess) return device_error("fp_sirt_step_multi", guard.status());
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    fp_status st;
+    size_t scratch_bytes = 0;
+    for (int k = 0; k < n_jobs; ++k) {
+        const fp_sirt_job &J = jobs[k];
+        const std::string tag = "fp_sirt_step_multi: job " + std::to_string(k);
+        if (!J.geometry) {
+            set_error(tag + " has no geometry");
+            return FP_ERR_INVALID_ARG;
+        }
+        if (J.geometry->device != dev) {
+            set_error(tag + " lives on another device");
+            return FP_ERR_INVALID_ARG;
+        }
+        if (!std::isfinite(J.relaxation)) {
+            set_error(tag + ": relaxation must be finite");
+            return FP_ERR_INVALID_ARG;
+        }
+        if ((st = check_device_ptr(J.image, dev, (tag + " image").c_str())) != FP_OK) return st;
+        if ((st = check_device_ptr(J.sino_meas, dev, (tag + " sino_meas").c_str())) != FP_OK) return st;
+        if ((st = check_device_ptr(J.work, dev, (tag + " work").c_str())) != FP_OK) return st;
+        if ((st = ensure_weights(const_cast<fp_geometry *>(J.geometry), s)) != FP_OK) return st;
+        scratch_bytes += (forward_work_bytes<float>(J.geometry->dev, 1) + 255) / 256 * 256;
+    }
+    Scratch scratch(dev, scratch_bytes, s);
+    if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step_multi", scratch.status());
+    char *base = static_cast<char *>(scratch.raw());
+    size_t off = 0;
+    for (int k0 = 0; k0 < n_jobs; k0 += kMaxJobsPerLaunch) {
+        MultiArgs args{};
+        args.n = std::min(kMaxJobsPerLaunch, n_jobs - k0);
+        unsigned fwd = 0, back = 0;
+        for (int k = 0; k < args.n; ++k) {
+            const fp_sirt_job &J = jobs[k0 + k];
+            const fp_geometry *g = J.geometry;
+            MultiJob &M = args.job[k];
+            M.g = g->dev;
+            const int nrows = std::max(g->nx, g->ny);
+            M.rows = reinterpret_cast<float *>(base + off);
+            M.cols = M.rows + (size_t)nrows * (g->nx + 2 * kFwdPad);
+            off += (forward_work_bytes<float>(g->dev, 1) + 255) / 256 * 256;
+            M.image = J.image;
+            M.image_out = J.image;
+            M.y_meas = J.sino_meas;
+            M.work = J.work;
+            M.row_w = g->row_w;
+            M.col_w = g->col_w;
+            M.relaxation = J.relaxation;
+            M.fwd_begin = fwd;
+            M.back_begin = back;
+            fwd += (unsigned)g->nv * (unsigned)((g->nd + kFwdThreads - 1) / kFwdThreads);
+            back += (unsigned)(g->dev.tiles_x * g->dev.tiles_y);
+        }
+        args.fwd_blocks = fwd;
+        args.back_blocks = back;
+        hipError_t e = launch_sirt_multi(args, s);
+        if (e != hipSuccess) return device_error("fp_sirt_step_multi: launch", e);
+    }
     return FP_OK;
 }

@@ -38,7 +38,7 @@ constexpr int kBackPad = 8;
 // Widest per-tile window with an unrolled cell loop.
 constexpr int kBackMaxUnrolled = 8;
 // Cell capacities (per view and tile) the back projection is instantiated for;
-// the LDS then holds (kBackRayParams + batch) arrays of that many floats.
+// the LDS then holds (kBackRayParams + batch) arrays of that many values.
 constexpr int kBackCaps[] = {64, 128, 256, 512, 1024};
 constexpr int kBackMaxCap = 1024;
 // LDS the back kernel may use per work-group (two staging buffers).
@@ -48,8 +48,23 @@ constexpr size_t kBackLdsLimit = 64 * 1024;
 constexpr int kBackGroupsPerCu = 8;
 constexpr int kBackMaxGroups = 8;
 
+// Per-ray constants, [nv][nd] each, in the kernels' arithmetic type: FP32
+// roundings of FP64 values for the production kernels, the FP64 values
+// themselves for the FP64 instantiation.
+template <typename Real>
+struct RayTables {
+    const Real *inv_r = nullptr;  // 1 / R_m,  R_m = |q(s_m) - p|
+    const Real *ghr = nullptr;    // g_m / (2 R_m): half effective blur per unit of R L
+    const Real *hab = nullptr;    // (a + b) / 2, a <= b the projected pixel widths
+    const Real *ia = nullptr;     // 1 / max(a, tiny)
+    const Real *nhbia = nullptr;  // -(b - a) / (2 max(a, tiny))
+    const Real *ha = nullptr;     // a / 2
+    const Real *wb = nullptr;     // delta^2 / (2 b)
+};
+constexpr int kRayTables = 7;
+
 // Read-only description of a geometry as the kernels see it.  All pointers
-// are device pointers into one allocation owned by fp_geometry.
+// are device pointers owned by fp_geometry.
 struct DevGeom {
     int nx, ny;              // image columns, rows
     int nv, nd;              // views, detector cells
@@ -62,40 +77,76 @@ struct DevGeom {
     double tau;              // cell width (= pitch)
     double half_diag;        // radius of a disk containing every pixel
     const double2 *views;    // [nv] (cos t, sin t)
-    // Per-ray constants, [nv][nd] each (FP32 roundings of FP64 values):
-    const float *inv_r;      // 1 / R_m,  R_m = |q(s_m) - p|
-    const float *ghr;        // g_m / (2 R_m): half effective blur per unit of R L
-    const float *hab;        // (a + b) / 2, a <= b the projected pixel widths
-    const float *ia;         // 1 / max(a, tiny)
-    const float *nhbia;      // -(b - a) / (2 max(a, tiny))
-    const float *ha;         // a / 2
-    const float *wb;         // delta^2 / (2 b)
+    RayTables<float> r32;
+    RayTables<double> r64;   // built on the first FP64 call
     // [nv][tiles_y * tiles_x]: first cell M0 and count of the cells the tile
     // can touch, the window width T every pixel of the tile evaluates, and
     // (as float bits) the bound H on |s_m - s_k| of its non-zero cells.
     const int4 *tile_cells;
 };
 
+template <typename Real>
+__host__ __device__ inline const RayTables<Real> &ray_tables(const DevGeom &g);
+template <>
+__host__ __device__ inline const RayTables<float> &ray_tables<float>(const DevGeom &g) {
+    return g.r32;
+}
+template <>
+__host__ __device__ inline const RayTables<double> &ray_tables<double>(const DevGeom &g) {
+    return g.r64;
+}
+
 enum class FwdMode : int { kPlain = 0, kSirtResidual = 1, kOnes = 2, kCount = 3 };
 enum class BackMode : int { kPlain = 0, kSirtUpdate = 1, kOnes = 2 };
 
-// Kernel launchers (projector.hip).  Return the hipError_t of the launch.
+// Kernel launchers (projector.hip), instantiated for Real = float and double.
+// Return the hipError_t of the launch.
 // launch_forward: `img` is the caller's [nb][ny][nx] image (unused by the
-// kOnes / kCount modes); `work` is device scratch of forward_work_bytes(g, nb)
+// kOnes / kCount modes); `work` is device scratch of forward_work_bytes
 // bytes for the padded copies.
-hipError_t launch_forward(const DevGeom &g, FwdMode mode, int nb, const float *img,
-                          float *work, float *out, int *counts, const float *y_meas,
-                          const float *row_w, hipStream_t stream);
+template <typename Real>
+hipError_t launch_forward(const DevGeom &g, FwdMode mode, int nb, const Real *img, Real *work,
+                          Real *out, int *counts, const Real *y_meas, const Real *row_w,
+                          hipStream_t stream);
+template <typename Real>
 size_t forward_work_bytes(const DevGeom &g, int nb);
-// launch_back: `partial` is device scratch of back_work_bytes(g, nb) bytes
-// (may be NULL, which forces a single view group).
-hipError_t launch_back(const DevGeom &g, BackMode mode, int nb, const float *sino,
-                       float *img, float *partial, const float *col_w, float relaxation,
-                       hipStream_t stream);
+// launch_back: `partial` is device scratch of back_work_bytes bytes (may be
+// NULL, which forces a single view group).
+template <typename Real>
+hipError_t launch_back(const DevGeom &g, BackMode mode, int nb, const Real *sino, Real *img,
+                       Real *partial, const Real *col_w, Real relaxation, hipStream_t stream);
+template <typename Real>
 size_t back_work_bytes(const DevGeom &g, int nb);
 // Largest batch chunk the back kernel's LDS holds for this geometry (0 if
 // even one image does not fit).
+template <typename Real>
 int back_max_batch(const DevGeom &g);
+
+// Grouped SIRT step: several jobs, each with its own geometry, in one launch
+// per phase (padded copies, forward residual, back update).  Up to
+// kMaxJobsPerLaunch job descriptors travel in the kernel arguments.
+constexpr int kMaxJobsPerLaunch = 12;
+struct MultiJob {
+    DevGeom g;
+    const float *image;     // [ny][nx] iterate, read by the forward phase
+    float *rows, *cols;     // padded copies (scratch)
+    float *image_out;       // the iterate, updated by the back phase
+    const float *y_meas;    // [nv][nd]
+    float *work;            // [nv][nd] residual R .* (y - A x)
+    const float *row_w, *col_w;
+    float relaxation;
+    unsigned fwd_begin;     // first forward work-group of this job
+    unsigned back_begin;    // first back work-group of this job
+};
+struct MultiArgs {
+    int n;
+    unsigned fwd_blocks, back_blocks;
+    MultiJob job[kMaxJobsPerLaunch];
+};
+static_assert(sizeof(MultiArgs) <= 4000, "kernel arguments must stay under 4 KB");
+// Launch the three phases for args.job[0 .. n); rows/cols/fwd_begin/
+// back_begin must be filled in.
+hipError_t launch_sirt_multi(const MultiArgs &args, hipStream_t stream);
 
 }  // namespace fanproj
 
@@ -105,8 +156,13 @@ struct fp_geometry {
     double pixel = 0, dsc = 0, dsd = 0, tau = 0;
     std::vector<double> angles;
     fanproj::DevGeom dev{};
-    void *table_block = nullptr;   // one device allocation for all tables
+    void *table_block = nullptr;   // one device allocation for the FP32 tables
     size_t table_bytes = 0;
+    // FP64 per-ray tables, built on the first FP64 call.
+    std::mutex f64_mu;
+    bool f64_ready = false;
+    void *f64_block = nullptr;
+    size_t f64_bytes = 0;
     // SIRT weights R = 1/(A 1) and C = 1/(A^T 1), built on first use.
     std::mutex weights_mu;
     bool weights_ready = false;
@@ -116,6 +172,11 @@ struct fp_geometry {
 };
 
 namespace fanproj {
+// FP64 values of the per-ray constants (RayTables field order), computed on
+// the host from the geometry.
+void compute_ray_constants(const fp_geometry &g, std::vector<double> (&out)[kRayTables]);
+// Uploads the FP64 per-ray tables if they are not there yet (thread-safe).
+fp_status ensure_f64_tables(fp_geometry *g);
 // Thread-local error text used by fp_last_error.
 void set_error(const std::string &msg);
 void clear_error();

@@ -17,6 +17,72 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 bool finite_positive(double x) { return std::isfinite(x) && x > 0.0; }
 
 }  // namespace
+
+void compute_ray_constants(const fp_geometry &g, std::vector<double> (&out)[kRayTables]) {
+    const size_t nr = (size_t)g.nv * g.nd;
+    for (auto &v : out) v.assign(nr, 0.0);
+    const double D = g.dsd, tau = g.tau, delta = g.pixel, c0 = 0.5 * (g.nd - 1);
+    for (int v = 0; v < g.nv; ++v) {
+        const double cs = std::cos(g.angles[v]), sn = std::sin(g.angles[v]);
+        // u = (cs, sn) towards the source; e = (sn, -cs) along the detector.
+        for (int m = 0; m < g.nd; ++m) {
+            const double s = (m - c0) * tau;
+            const double R = std::sqrt(D * D + s * s);
+            // w_perp = (D e + s u) / R: unit normal of the ray through s.
+            const double wpx = (D * sn + s * cs) / R;
+            const double wpy = (-D * cs + s * sn) / R;
+            const double z1 = delta * std::fabs(wpx), z2 = delta * std::fabs(wpy);
+            const double a = std::min(z1, z2), b = std::max(z1, z2);
+            // eq. (17): tau' = L * (tan_hi - tan_lo) with
+            // tan_(+-) = D (s_(+-) - s) / (D^2 + s s_(+-)), s_(+-) = s +- tau/2.
+            const double gm = 0.5 * tau * D *
+                              (1.0 / (D * D + s * (s + 0.5 * tau)) +
+                               1.0 / (D * D + s * (s - 0.5 * tau)));
+            const double a_safe = std::max(a, 1e-30);
+            const size_t r = (size_t)v * g.nd + m;
+            out[0][r] = 1.0 / R;                        // inv_r
+            out[1][r] = gm / (2.0 * R);                 // ghr
+            out[2][r] = 0.5 * (a + b);                  // hab
+            out[3][r] = 1.0 / a_safe;                   // ia
+            out[4][r] = -0.5 * (b - a) / a_safe;        // nhbia
+            out[5][r] = 0.5 * a;                        // ha
+            out[6][r] = delta * delta / (2.0 * b);      // wb
+        }
+    }
+}
+
+fp_status ensure_f64_tables(fp_geometry *g) {
+    std::lock_guard<std::mutex> lock(g->f64_mu);
+    if (g->f64_ready) return FP_OK;
+    const size_t nr = (size_t)g->nv * g->nd;
+    std::vector<double> rays64[kRayTables];
+    compute_ray_constants(*g, rays64);
+    const size_t per = align_up(nr * sizeof(double), 256);
+    const size_t bytes = per * kRayTables;
+    hipError_t e = hipMalloc(&g->f64_block, bytes);
+    if (e != hipSuccess) {
+        g->f64_block = nullptr;
+        (void)hipGetLastError();
+        set_error("FP64 tables: hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return FP_ERR_OUT_OF_MEMORY;
+    }
+    std::vector<char> host(bytes, 0);
+    for (int k = 0; k < kRayTables; ++k)
+        std::memcpy(host.data() + k * per, rays64[k].data(), nr * sizeof(double));
+    e = hipMemcpy(g->f64_block, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(g->f64_block);
+        g->f64_block = nullptr;
+        return device_error("FP64 tables: upload", e);
+    }
+    const char *base = static_cast<const char *>(g->f64_block);
+    const double *t[kRayTables];
+    for (int k = 0; k < kRayTables; ++k) t[k] = reinterpret_cast<const double *>(base + k * per);
+    g->dev.r64 = RayTables<double>{t[0], t[1], t[2], t[3], t[4], t[5], t[6]};
+    g->f64_bytes = bytes;
+    g->f64_ready = true;
+    return FP_OK;
+}
 }  // namespace fanproj
 
 using namespace fanproj;
@@ -73,40 +139,16 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
 
     // ---- host tables (FP64 arithmetic) ----
     std::vector<double> views(2 * (size_t)n_views);
-    std::vector<float> inv_r(nr), ghr(nr), hab(nr), ia(nr), nhbia(nr), ha(nr), wb(nr);
     std::vector<int32_t> tile_cells(4 * (size_t)n_views * ntiles);
     const double D = dist_source_detector, tau = det_width, delta = pixel_size;
     const double c0 = 0.5 * (n_det - 1);
     int max_cells = 0;
     for (int v = 0; v < n_views; ++v) {
-        const double cs = std::cos(view_angles[v]), sn = std::sin(view_angles[v]);
-        views[2 * v] = cs;
-        views[2 * v + 1] = sn;
-        // u = (cs, sn) towards the source; e = (sn, -cs) along the detector.
-        for (int m = 0; m < n_det; ++m) {
-            const double s = (m - c0) * tau;
-            const double R = std::sqrt(D * D + s * s);
-            // w_perp = (D e + s u) / R: unit normal of the ray through s.
-            const double wpx = (D * sn + s * cs) / R;
-            const double wpy = (-D * cs + s * sn) / R;
-            const double z1 = delta * std::fabs(wpx), z2 = delta * std::fabs(wpy);
-            const double a = std::min(z1, z2), b = std::max(z1, z2);
-            // eq. (17): tau' = L * (tan_hi - tan_lo) with
-            // tan_(+-) = D (s_(+-) - s) / (D^2 + s s_(+-)), s_(+-) = s +- tau/2.
-            const double gm = 0.5 * tau * D *
-                              (1.0 / (D * D + s * (s + 0.5 * tau)) +
-                               1.0 / (D * D + s * (s - 0.5 * tau)));
-            const size_t r = (size_t)v * n_det + m;
-            inv_r[r] = (float)(1.0 / R);
-            ghr[r] = (float)(gm / (2.0 * R));
-            const double a_safe = std::max(a, 1e-30);
-            hab[r] = (float)(0.5 * (a + b));
-            ia[r] = (float)(1.0 / a_safe);
-            nhbia[r] = (float)(-0.5 * (b - a) / a_safe);
-            ha[r] = (float)(0.5 * a);
-            wb[r] = (float)(delta * delta / (2.0 * b));
-        }
+        views[2 * v] = std::cos(view_angles[v]);
+        views[2 * v + 1] = std::sin(view_angles[v]);
     }
+    std::vector<double> rays64[kRayTables];
+    compute_ray_constants(*g, rays64);
     // Largest half effective blur anywhere: tau'/2 = g_m L / 2 with
     // L <= D_sc D / R_m + (radius of the image) <= D_sc + half_diag + delta.
     double gmax = 0.0;
@@ -196,7 +238,6 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     const size_t A = 256;
     size_t off = 0;
     const size_t off_views = off; off = align_up(off + views.size() * sizeof(double), A);
-    constexpr int kRayTables = 7;
     size_t off_rays[kRayTables];
     for (int k = 0; k < kRayTables; ++k) { off_rays[k] = off; off = align_up(off + nr * sizeof(float), A); }
     const size_t off_tiles = off; off = align_up(off + tile_cells.size() * sizeof(int32_t), A);
@@ -218,7 +259,7 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
                   "; cells too narrow for the pixel size)");
         return FP_ERR_UNSUPPORTED;
     }
-    if (back_max_batch(d) < 1) {
+    if (back_max_batch<float>(d) < 1) {
         set_error("fp_geometry_create: a back-projection tile spans " + std::to_string(max_cells) +
                   " cells, more than the on-chip staging holds");
         return FP_ERR_UNSUPPORTED;
@@ -246,9 +287,10 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     char *base = static_cast<char *>(g->table_block);
     std::vector<char> host(g->table_bytes, 0);
     std::memcpy(host.data() + off_views, views.data(), views.size() * sizeof(double));
-    const std::vector<float> *rays[kRayTables] = {&inv_r, &ghr, &hab, &ia, &nhbia, &ha, &wb};
-    for (int k = 0; k < kRayTables; ++k)
-        std::memcpy(host.data() + off_rays[k], rays[k]->data(), nr * sizeof(float));
+    for (int k = 0; k < kRayTables; ++k) {
+        float *dst = reinterpret_cast<float *>(host.data() + off_rays[k]);
+        for (size_t r = 0; r < nr; ++r) dst[r] = (float)rays64[k][r];
+    }
     std::memcpy(host.data() + off_tiles, tile_cells.data(), tile_cells.size() * sizeof(int32_t));
     e = hipMemcpy(base, host.data(), g->table_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -256,13 +298,10 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
         return device_error("fp_geometry_create: table upload", e);
     }
     d.views = reinterpret_cast<const double2 *>(base + off_views);
-    d.inv_r = reinterpret_cast<const float *>(base + off_rays[0]);
-    d.ghr = reinterpret_cast<const float *>(base + off_rays[1]);
-    d.hab = reinterpret_cast<const float *>(base + off_rays[2]);
-    d.ia = reinterpret_cast<const float *>(base + off_rays[3]);
-    d.nhbia = reinterpret_cast<const float *>(base + off_rays[4]);
-    d.ha = reinterpret_cast<const float *>(base + off_rays[5]);
-    d.wb = reinterpret_cast<const float *>(base + off_rays[6]);
+    const float *fr[kRayTables];
+    for (int k = 0; k < kRayTables; ++k) fr[k] = reinterpret_cast<const float *>(base + off_rays[k]);
+    d.r32 = RayTables<float>{fr[0], fr[1], fr[2], fr[3], fr[4], fr[5], fr[6]};
+    d.r64 = RayTables<double>{};
     d.tile_cells = reinterpret_cast<const int4 *>(base + off_tiles);
     *out = g.release();
     return FP_OK;
@@ -277,6 +316,7 @@ extern "C" fp_status fp_geometry_destroy(fp_geometry *g) {
     if (e == hipSuccess) e = hipDeviceSynchronize();
     hipError_t f = hipSuccess;
     if (g->table_block) f = hipFree(g->table_block);
+    if (g->f64_block) (void)hipFree(g->f64_block);
     if (g->row_w) (void)hipFree(g->row_w);
     if (g->col_w) (void)hipFree(g->col_w);
     if (cur != g->device) (void)hipSetDevice(cur);
@@ -288,5 +328,5 @@ extern "C" fp_status fp_geometry_destroy(fp_geometry *g) {
 
 extern "C" size_t fp_geometry_device_bytes(const fp_geometry *g) {
     if (!g) return 0;
-    return g->table_bytes + g->weight_bytes;
+    return g->table_bytes + g->f64_bytes + g->weight_bytes;
 }

@@ -39,8 +39,23 @@ _lib.fp_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
 _lib.fp_forward.restype = ctypes.c_int
 _lib.fp_back.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
 _lib.fp_back.restype = ctypes.c_int
+_lib.fp_forward_f64.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
+_lib.fp_forward_f64.restype = ctypes.c_int
+_lib.fp_back_f64.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
+_lib.fp_back_f64.restype = ctypes.c_int
 _lib.fp_sirt_step.argtypes = [_vp, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32, _vp]
 _lib.fp_sirt_step.restype = ctypes.c_int
+class FpSirtJob(ctypes.Structure):
+    """fp_sirt_job of the C ABI."""
+    _fields_ = [("geometry", ctypes.c_void_p), ("image", ctypes.c_void_p),
+                ("sino_meas", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("relaxation", ctypes.c_float)]
+
+
+_lib.fp_sirt_prepare.argtypes = [_vp, _vp]
+_lib.fp_sirt_prepare.restype = ctypes.c_int
+_lib.fp_sirt_step_multi.argtypes = [ctypes.POINTER(FpSirtJob), ctypes.c_int32, _vp]
+_lib.fp_sirt_step_multi.restype = ctypes.c_int
 _lib.fp_count_nonzero.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp]
 _lib.fp_count_nonzero.restype = ctypes.c_int
 _lib.fp_geometry_device_bytes.argtypes = [_vp]
@@ -48,7 +63,8 @@ _lib.fp_geometry_device_bytes.restype = ctypes.c_size_t
 _lib.fp_last_error.argtypes = []
 _lib.fp_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ("fp_geometry_create", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_sirt_step",
+EXPORTED = ("fp_geometry_create", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_forward_f64",
+            "fp_back_f64", "fp_sirt_step", "fp_sirt_prepare", "fp_sirt_step_multi",
             "fp_count_nonzero", "fp_geometry_device_bytes", "fp_last_error")
 
 
@@ -74,12 +90,13 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dev_ptr(t, name, shape=None):
+def _dev_ptr(t, name, shape=None, dtype=None):
     import torch
+    dtype = torch.float32 if dtype is None else dtype
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
-        raise ValueError(f"{name} must be a contiguous float32 tensor on a GPU")
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on a GPU")
     if shape is not None and tuple(t.shape[-len(shape):]) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., {shape})")
     return ctypes.c_void_p(t.data_ptr())
@@ -112,10 +129,38 @@ def fp_back(handle, sino, image, batch, stream=None) -> None:
                         _stream_handle(stream)))
 
 
+def fp_forward_f64(handle, image, sino, batch, stream=None) -> None:
+    import torch
+    _check(_lib.fp_forward_f64(handle, _dev_ptr(image, "image", dtype=torch.float64),
+                               _dev_ptr(sino, "sino", dtype=torch.float64), int(batch),
+                               _stream_handle(stream)))
+
+
+def fp_back_f64(handle, sino, image, batch, stream=None) -> None:
+    import torch
+    _check(_lib.fp_back_f64(handle, _dev_ptr(sino, "sino", dtype=torch.float64),
+                            _dev_ptr(image, "image", dtype=torch.float64), int(batch),
+                            _stream_handle(stream)))
+
+
 def fp_sirt_step(handle, image, sino_meas, relaxation, work, batch, stream=None) -> None:
     _check(_lib.fp_sirt_step(handle, _dev_ptr(image, "image"), _dev_ptr(sino_meas, "sino_meas"),
                              float(relaxation), _dev_ptr(work, "work"), int(batch),
                              _stream_handle(stream)))
+
+
+def fp_sirt_prepare(handle, stream=None) -> None:
+    _check(_lib.fp_sirt_prepare(handle, _stream_handle(stream)))
+
+
+def fp_sirt_step_multi(jobs, stream=None) -> None:
+    """jobs: sequence of (handle, image, sino_meas, work, relaxation), batch 1 each."""
+    arr = (FpSirtJob * max(len(jobs), 1))()
+    for k, (h, image, sino_meas, work, relax) in enumerate(jobs):
+        arr[k] = FpSirtJob(h.value if isinstance(h, ctypes.c_void_p) else h,
+                           _dev_ptr(image, "image").value, _dev_ptr(sino_meas, "sino_meas").value,
+                           _dev_ptr(work, "work").value, float(relax))
+    _check(_lib.fp_sirt_step_multi(arr, len(jobs), _stream_handle(stream)))
 
 
 def fp_count_nonzero(handle, stream=None) -> int:
@@ -164,21 +209,24 @@ class Geometry:
         return t.shape[0]
 
     def forward(self, image, out=None, stream=None):
+        """A c for float32 (production kernels) or float64 (FP64 kernels)."""
         import torch
         b = self._batch(image, (self.ny, self.nx), "image")
         if out is None:
             shape = (self.n_views, self.n_det) if image.dim() == 2 else (b, self.n_views, self.n_det)
-            out = torch.empty(shape, dtype=torch.float32, device=image.device)
-        fp_forward(self.handle, image, out, b, stream)
+            out = torch.empty(shape, dtype=image.dtype, device=image.device)
+        (fp_forward_f64 if image.dtype == torch.float64 else fp_forward)(self.handle, image, out, b,
+                                                                          stream)
         return out
 
     def back(self, sino, out=None, stream=None):
+        """A^T y for float32 (production kernels) or float64 (FP64 kernels)."""
         import torch
         b = self._batch(sino, (self.n_views, self.n_det), "sino")
         if out is None:
             shape = (self.ny, self.nx) if sino.dim() == 2 else (b, self.ny, self.nx)
-            out = torch.empty(shape, dtype=torch.float32, device=sino.device)
-        fp_back(self.handle, sino, out, b, stream)
+            out = torch.empty(shape, dtype=sino.dtype, device=sino.device)
+        (fp_back_f64 if sino.dtype == torch.float64 else fp_back)(self.handle, sino, out, b, stream)
         return out
 
     def sirt_step(self, image, sino_meas, relaxation=1.0, work=None, stream=None):

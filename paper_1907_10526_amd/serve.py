@@ -1,0 +1,279 @@
+"""Serving reconstruction jobs with continuous batching.
+
+A job is a SIRT reconstruction (the iterative family the projector serves,
+Sec. I): a fan-beam geometry, a sinogram and a number of iterations.  Jobs
+arrive over time with different image sizes, view counts and detector counts.
+
+``Server.run`` is the request loop:
+
+* arrived jobs wait in a FIFO queue and are admitted while the device-memory
+  budget and the slot limit allow (admission by free HBM);
+* an admitted job keeps its geometry tables, iterate, sinogram and scratch on
+  the device until it finishes;
+* every step advances *all* admitted jobs by one SIRT iteration in grouped
+  launches (``fp_sirt_step_multi``: one launch per phase for up to 12 jobs of
+  different geometries), so jobs that arrive while others run join at the next
+  step and their work overlaps on the device (continuous batching);
+* finished jobs leave and free their memory for the queue.
+
+``run_plain`` is the comparison path: one job at a time, in arrival order,
+with ``fp_sirt_step``.
+
+The scheduler only talks to an executor (``prepare``, ``step``, ``run_job``,
+``result``, ``release``)
+and a clock, so its admission and ordering logic can be tested on the CPU
+with a scripted executor and a simulated clock.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = ["JobSpec", "make_trace", "job_device_bytes", "RealClock", "SimClock", "Server",
+           "run_plain", "latency_stats", "GpuExecutor"]
+
+
+@dataclass
+class JobSpec:
+    job_id: int
+    arrival: float          # seconds after the start of the trace
+    n: int                  # image side (n x n, pixel size 1)
+    n_views: int            # views uniformly over [0, 2 pi)
+    n_det: int              # detector cells of width det_width
+    dsc: float              # source-to-centre distance
+    dsd: float              # source-to-detector distance
+    iters: int = 20
+    det_width: float = 1.0
+    seed: int = 0           # seed of the job's data
+
+    def geometry_kwargs(self) -> dict:
+        ang = 2.0 * np.pi * np.arange(self.n_views, dtype=np.float64) / self.n_views
+        return dict(nx=self.n, ny=self.n, pixel=1.0, dsc=self.dsc, dsd=self.dsd, angles=ang,
+                    n_det=self.n_det, det_width=self.det_width)
+
+
+def make_trace(count: int, rate: float, seed: int, sizes=(256, 512, 1024),
+               views=(180, 360, 720, 1440), iters: int = 20) -> list:
+    """Seeded Poisson arrivals (exponential gaps, mean 1/rate) of jobs with
+    image side from `sizes`, views from `views`, detectors = 2 x side,
+    source-centre U[2, 4] x side and magnification 1.5."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(rng.choice(sizes))
+        nv = int(rng.choice(views))
+        dsc = float(rng.uniform(2.0, 4.0)) * n
+        out.append(JobSpec(job_id=k, arrival=t, n=n, n_views=nv, n_det=2 * n, dsc=dsc,
+                           dsd=1.5 * dsc, iters=iters, seed=int(rng.integers(0, 2 ** 31))))
+    return out
+
+
+def job_device_bytes(spec: JobSpec) -> int:
+    """Upper estimate of the device memory a job holds while admitted: the
+    FP32 per-ray tables (7 per ray), per-view and per-tile tables, the SIRT
+    weights, iterate, sinogram, residual and the padded image copies."""
+    rays = spec.n_views * spec.n_det
+    pix = spec.n * spec.n
+    tiles = math.ceil(spec.n / 16) * math.ceil(spec.n / 32)
+    tables = 4 * 7 * rays + 16 * spec.n_views + 16 * spec.n_views * tiles
+    weights = 4 * (rays + pix)
+    buffers = 4 * (pix + 2 * rays)
+    pad = 4 * spec.n * 2 * (spec.n + 32)
+    return tables + weights + buffers + pad + 4 * 4096
+
+
+class RealClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def wait_until(self, t: float) -> None:
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(dt)
+
+
+class SimClock:
+    """Simulated time: advances only when told to (scripted executors)."""
+
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def advance(self, dt: float) -> None:
+        self.t += dt
+
+    def wait_until(self, t: float) -> None:
+        self.t = max(self.t, t)
+
+
+@dataclass
+class _Active:
+    spec: JobSpec
+    handle: object
+    nbytes: int
+    admitted: float
+    done_iters: int = 0
+
+
+@dataclass
+class ServeResult:
+    latency: dict = field(default_factory=dict)     # job_id -> completion - arrival
+    admitted: dict = field(default_factory=dict)    # job_id -> admission time
+    finished: dict = field(default_factory=dict)    # job_id -> completion time
+    order: list = field(default_factory=list)       # job ids in admission order
+    steps: int = 0
+    peak_active: int = 0
+    peak_bytes: int = 0
+    makespan: float = 0.0
+    outputs: dict = field(default_factory=dict)     # job_id -> final iterate (if kept)
+
+
+class Server:
+    """Continuous-batching request loop over an executor.
+
+    hbm_budget: bytes the admitted jobs may hold together (a job larger than
+    the budget is admitted alone when nothing else runs); max_active: slot
+    limit.
+    """
+
+    def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
+                 clock=None, keep_outputs: bool = False):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_active = int(max_active)
+        self.clock = clock or RealClock()
+        self.keep_outputs = keep_outputs
+
+    def run(self, trace) -> ServeResult:
+        res = ServeResult()
+        pending = deque(sorted(trace, key=lambda s: (s.arrival, s.job_id)))
+        waiting = deque()
+        active: list = []
+        used = 0
+        clock = self.clock
+        while pending or waiting or active:
+            now = clock.now()
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission by free device memory, FIFO (no overtaking)
+            while waiting and len(active) < self.max_active:
+                spec = waiting[0]
+                need = job_device_bytes(spec)
+                if active and used + need > self.budget:
+                    break
+                waiting.popleft()
+                handle = self.ex.prepare(spec)
+                active.append(_Active(spec, handle, need, clock.now()))
+                used += need
+                res.admitted[spec.job_id] = clock.now()
+                res.order.append(spec.job_id)
+            res.peak_active = max(res.peak_active, len(active))
+            res.peak_bytes = max(res.peak_bytes, used)
+            if not active:
+                if pending:
+                    clock.wait_until(pending[0].arrival)
+                continue
+            # one SIRT iteration for every admitted job, in grouped launches
+            self.ex.step([a.handle for a in active])
+            res.steps += 1
+            t_done = clock.now()
+            still = []
+            for a in active:
+                a.done_iters += 1
+                if a.done_iters >= a.spec.iters:
+                    res.finished[a.spec.job_id] = t_done
+                    res.latency[a.spec.job_id] = t_done - a.spec.arrival
+                    if self.keep_outputs:
+                        res.outputs[a.spec.job_id] = self.ex.result(a.handle)
+                    self.ex.release(a.handle)
+                    used -= a.nbytes
+                else:
+                    still.append(a)
+            active = still
+        res.makespan = clock.now()
+        return res
+
+
+def run_plain(executor, trace, clock=None, keep_outputs: bool = False) -> ServeResult:
+    """The plain path: one job at a time in arrival order, each run to the end
+    with single-job SIRT steps."""
+    clock = clock or RealClock()
+    res = ServeResult()
+    for spec in sorted(trace, key=lambda s: (s.arrival, s.job_id)):
+        clock.wait_until(spec.arrival)
+        h = executor.prepare(spec)
+        res.admitted[spec.job_id] = clock.now()
+        res.order.append(spec.job_id)
+        executor.run_job(h, spec.iters)
+        res.steps += spec.iters
+        t = clock.now()
+        res.finished[spec.job_id] = t
+        res.latency[spec.job_id] = t - spec.arrival
+        if keep_outputs:
+            res.outputs[spec.job_id] = executor.result(h)
+        executor.release(h)
+    res.peak_active = 1
+    res.makespan = clock.now()
+    return res
+
+
+def latency_stats(res: ServeResult) -> dict:
+    lat = np.array(sorted(res.latency.values()))
+    n = len(lat)
+    return {"jobs": n, "p50_s": float(np.percentile(lat, 50)) if n else None,
+            "p99_s": float(np.percentile(lat, 99)) if n else None,
+            "mean_s": float(lat.mean()) if n else None,
+            "makespan_s": res.makespan, "throughput_jobs_per_s": n / res.makespan if res.makespan else None,
+            "steps": res.steps, "peak_active": res.peak_active}
+
+
+class GpuExecutor:
+    """Executor on one GPU through the C ABI: each job gets its own geometry,
+    an iterate starting at zero, a seeded sinogram U[0, 4] and a residual
+    buffer, all on the device."""
+
+    def __init__(self, device="cuda"):
+        import torch
+
+        from . import fanproj
+        self.torch = torch
+        self.fp = fanproj
+        self.device = torch.device(device)
+
+    def prepare(self, spec: JobSpec):
+        torch = self.torch
+        g = self.fp.Geometry(**spec.geometry_kwargs())
+        gen = torch.Generator(device=self.device).manual_seed(spec.seed)
+        y = torch.rand((g.n_views, g.n_det), generator=gen, device=self.device) * 4.0
+        x = torch.zeros((g.ny, g.nx), device=self.device)
+        w = torch.empty_like(y)
+        self.fp.fp_sirt_prepare(g.handle)
+        return (g, x, y, w)
+
+    def step(self, handles) -> None:
+        self.fp.fp_sirt_step_multi([(g.handle, x, y, w, 1.0) for g, x, y, w in handles])
+        self.torch.cuda.synchronize(self.device)
+
+    def run_job(self, h, iters: int) -> None:
+        g, x, y, w = h
+        for _ in range(iters):
+            g.sirt_step(x, y, 1.0, w)
+        self.torch.cuda.synchronize(self.device)
+
+    def result(self, h):
+        return h[1].detach().clone()
+
+    def release(self, h) -> None:
+        g = h[0]
+        g.close()
