@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfanproj.so")
-SOURCES = ["projector.hip", "geometry.cpp", "abi.cpp"]
+SOURCES = ["projector.hip", "tables.hip", "geometry.cpp", "abi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -172,9 +172,6 @@ struct fp_geometry {
 };
 
 namespace fanproj {
-// FP64 values of the per-ray constants (RayTables field order), computed on
-// the host from the geometry.
-void compute_ray_constants(const fp_geometry &g, std::vector<double> (&out)[kRayTables]);
 // Uploads the FP64 per-ray tables if they are not there yet (thread-safe).
 fp_status ensure_f64_tables(fp_geometry *g);
 // Thread-local error text used by fp_last_error.

@@ -10,10 +10,13 @@ arrive over time with different image sizes, view counts and detector counts.
   budget and the slot limit allow (admission by free HBM);
 * an admitted job keeps its geometry tables, iterate, sinogram and scratch on
   the device until it finishes;
-* every step advances *all* admitted jobs by one SIRT iteration in grouped
-  launches (``fp_sirt_step_multi``: one launch per phase for up to 12 jobs of
-  different geometries), so jobs that arrive while others run join at the next
-  step and their work overlaps on the device (continuous batching);
+* every step advances admitted jobs by one SIRT iteration in grouped launches
+  (``fp_sirt_step_multi``: one launch per phase for up to 12 jobs of different
+  geometries), so jobs that arrive while others run join at the next step and
+  their work overlaps on the device (continuous batching).  A step takes the
+  admitted jobs, oldest first, whose summed work per iteration fits a budget
+  (always at least the oldest job): enough small jobs to fill the device, without
+  stretching an old job's iterations by the work of every younger one;
 * finished jobs leave and free their memory for the queue.
 
 ``run_plain`` is the comparison path: one job at a time, in arrival order,
@@ -33,7 +36,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["JobSpec", "make_trace", "job_device_bytes", "RealClock", "SimClock", "Server",
+__all__ = ["JobSpec", "make_trace", "job_device_bytes", "job_iteration_work", "RealClock", "SimClock", "Server",
            "run_plain", "latency_stats", "GpuExecutor"]
 
 
@@ -72,6 +75,12 @@ def make_trace(count: int, rate: float, seed: int, sizes=(256, 512, 1024),
         out.append(JobSpec(job_id=k, arrival=t, n=n, n_views=nv, n_det=2 * n, dsc=dsc,
                            dsd=1.5 * dsc, iters=iters, seed=int(rng.integers(0, 2 ** 31))))
     return out
+
+
+def job_iteration_work(spec: JobSpec) -> float:
+    """Matrix entries one SIRT iteration of the job evaluates (a forward and a
+    back projection, about 3 non-zero cells per pixel and view)."""
+    return 2.0 * 3.0 * spec.n * spec.n * spec.n_views
 
 
 def job_device_bytes(spec: JobSpec) -> int:
@@ -137,6 +146,7 @@ class ServeResult:
     peak_bytes: int = 0
     makespan: float = 0.0
     outputs: dict = field(default_factory=dict)     # job_id -> final iterate (if kept)
+    batch_sizes: list = field(default_factory=list) # jobs per step
 
 
 class Server:
@@ -148,10 +158,11 @@ class Server:
     """
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
-                 clock=None, keep_outputs: bool = False):
+                 step_work: float = 4e9, clock=None, keep_outputs: bool = False):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
+        self.step_work = float(step_work)
         self.clock = clock or RealClock()
         self.keep_outputs = keep_outputs
 
@@ -184,12 +195,27 @@ class Server:
                 if pending:
                     clock.wait_until(pending[0].arrival)
                 continue
-            # one SIRT iteration for every admitted job, in grouped launches
-            self.ex.step([a.handle for a in active])
+            # one SIRT iteration for the oldest admitted jobs that fit the
+            # step's work budget, in grouped launches
+            # (first fit in admission order: the oldest job always goes, a
+            # job that does not fit leaves room for younger, smaller ones)
+            batch, work = [], 0.0
+            for a in active:     # admission order = arrival order
+                w = job_iteration_work(a.spec)
+                if batch and work + w > self.step_work:
+                    continue
+                batch.append(a)
+                work += w
+            self.ex.step([a.handle for a in batch])
             res.steps += 1
+            res.batch_sizes.append(len(batch))
             t_done = clock.now()
+            stepped = {id(a) for a in batch}
             still = []
             for a in active:
+                if id(a) not in stepped:
+                    still.append(a)
+                    continue
                 a.done_iters += 1
                 if a.done_iters >= a.spec.iters:
                     res.finished[a.spec.job_id] = t_done
@@ -235,7 +261,8 @@ def latency_stats(res: ServeResult) -> dict:
             "p99_s": float(np.percentile(lat, 99)) if n else None,
             "mean_s": float(lat.mean()) if n else None,
             "makespan_s": res.makespan, "throughput_jobs_per_s": n / res.makespan if res.makespan else None,
-            "steps": res.steps, "peak_active": res.peak_active}
+            "steps": res.steps, "peak_active": res.peak_active,
+            "mean_batch": float(np.mean(res.batch_sizes)) if res.batch_sizes else 1.0}
 
 
 class GpuExecutor:

@@ -126,3 +126,59 @@ def test_late_arrivals_join_running_batch():
     res = serve.Server(ex, hbm_budget=1 << 40, clock=clock).run([first, late])
     assert res.admitted[1] < res.finished[0]
     assert res.finished[1] < res.finished[0]
+
+
+def test_step_work_budget_keeps_fifo_priority():
+    """With a per-step work budget, each step holds the oldest admitted job
+    and younger jobs in admission order while their work fits."""
+    clock = serve.SimClock()
+    ex = FakeExecutor(clock)
+    trace = _trace(count=30, rate=200.0, iters=8)
+    big = max(serve.job_iteration_work(s) for s in trace)
+    res = serve.Server(ex, hbm_budget=1 << 40, step_work=big, clock=clock).run(trace)
+    assert len(res.latency) == 30
+    order = {j: k for k, j in enumerate(res.order)}
+    live = set()
+    for kind, handles, _ in ex.log:
+        if kind == "prepare":
+            live.add(handles)
+        elif kind == "release":
+            live.discard(handles)
+        else:
+            ks = [order[h] for h in handles]
+            assert ks == sorted(ks)                           # admission order
+            assert ks[0] == min(order[h] for h in live)       # the oldest live job
+            tot = sum(serve.job_iteration_work(trace[h]) for h in handles)
+            assert len(handles) == 1 or tot <= big
+
+
+class SaturatingExecutor(FakeExecutor):
+    """A step costs the launch overhead plus its total work at the device's
+    full rate, but never less than the time of `sat` work: a step with little
+    work leaves the device partly idle."""
+
+    def __init__(self, clock, sat=0.02, **kw):
+        super().__init__(clock, **kw)
+        self.sat = sat
+
+    def step(self, handles):
+        tot = sum(self.work(self.live[h]) for h in handles)
+        self.clock.advance(self.overhead + max(tot, self.sat) / self.width)
+        self.log.append(("step", tuple(handles), self.clock.now()))
+
+
+def test_work_budget_improves_median_over_unbounded_batching():
+    """Once a step's work fills the device, taking every admitted job into
+    each step only stretches the older jobs: with the same throughput, the
+    bounded step finishes jobs earlier."""
+    trace = _trace(count=80, rate=150.0, iters=10)
+    sat = max(SaturatingExecutor(None).work(s) for s in trace)
+    runs = {}
+    big = max(serve.job_iteration_work(s) for s in trace)
+    for name, budget in (("unbounded", 1e30), ("bounded", 2.0 * big)):
+        c = serve.SimClock()
+        runs[name] = serve.Server(SaturatingExecutor(c, sat=sat), hbm_budget=1 << 40,
+                                  step_work=budget, clock=c).run(trace)
+    a, b = serve.latency_stats(runs["unbounded"]), serve.latency_stats(runs["bounded"])
+    assert b["p50_s"] < a["p50_s"]
+    assert b["makespan_s"] <= a["makespan_s"] * 1.05
