@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "libcnsf_oracle.so")
 
 FAN_FLAT = 0
 PARALLEL = 1
+FAN_ARC = 2
 
 
 def build(force: bool = True) -> str:
@@ -109,13 +110,15 @@ def threads() -> int:
 
 
 class Geometry:
-    """Fan-beam (flat detector) or parallel-beam scan description.
+    """Fan-beam (flat or arc detector) or parallel-beam scan description.
 
     Pixel (i, j) is centred at ((i-(nx-1)/2) delta, (j-(ny-1)/2) delta); cell m
     at s_m = (m-(n_det-1)/2) * det_spacing on the detector axis
     (sin t, -cos t); the source of view t sits at dsc * (cos t, sin t) and the
     flat detector is perpendicular to that direction at distance dsd from the
-    source (Sec. II-A).
+    source (Sec. II-A).  With mode=FAN_ARC the cells lie on the circle of
+    radius dsd around the source and s is arc length on it; with
+    mode=PARALLEL every ray of a view runs along -(cos t, sin t).
     """
 
     def __init__(self, nx, ny, pixel, dsc, dsd, angles, n_det, det_width,

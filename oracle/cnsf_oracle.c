@@ -38,8 +38,15 @@
  *   - a zero direction is dropped (delta distribution, Sec. IV-A);
  *   - cells outside the detector do not exist (no extrapolation).
  *
- * Parallel-beam mode (Theorem 1) is provided for the exact pins: there every
- * ray of a view has direction -u, s' = e.k - s_m and tau' = tau.
+ * Parallel-beam mode (Theorem 1): every ray of a view has direction -u,
+ * s' = e.k - s_m and tau' = tau.
+ *
+ * Arc-detector mode (the paper notes that an arc detector is a special case
+ * of the same derivation, Sec. I): the cells lie on the circle of radius D_sd
+ * around the source, the detector coordinate s is arc length on that circle
+ * (so the ray of cell m leaves the central ray at the angle s_m / D_sd), and
+ * the bin edges are the two points at s_m -/+ tau/2 on the arc.  Eq. (13),
+ * (16)-(18) are then applied unchanged to that ray and those two edges.
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,6 +59,7 @@
 
 #define ORACLE_FAN_FLAT 0
 #define ORACLE_PARALLEL 1
+#define ORACLE_FAN_ARC 2
 
 typedef struct {
     int32_t nx, ny;          /* image columns (x) and rows (y)              */
@@ -63,7 +71,8 @@ typedef struct {
     int32_t n_det;           /* detector cells                              */
     double det_spacing;      /* cell pitch Delta_s                          */
     double det_width;        /* bin width tau                               */
-    int32_t mode;            /* ORACLE_FAN_FLAT or ORACLE_PARALLEL          */
+    int32_t mode;            /* ORACLE_FAN_FLAT, ORACLE_PARALLEL or
+                                ORACLE_FAN_ARC                              */
 } oracle_geom;
 
 /* ------------------------------------------------------------------------ */
@@ -128,7 +137,8 @@ double oracle_box2(double x, double w1, double w2)
 /* Geometry (Sec. II-A, eq. (13), eq. (17)).                                 */
 /* ------------------------------------------------------------------------ */
 
-/* Centre of detector cell m along the detector axis. */
+/* Centre of detector cell m along the detector axis (arc length on the arc
+ * detector). */
 static double cell_centre(const oracle_geom *g, int m)
 {
     return ((double)m - 0.5 * (double)(g->n_det - 1)) * g->det_spacing;
@@ -151,6 +161,19 @@ typedef struct {
     double edge_lo[2], edge_hi[2];   /* (x1, x2) of q(s_m -/+ tau/2) - p     */
 } ray_frame;
 
+static void detector_offset(const oracle_geom *g, const double u[2], const double e[2],
+                            double s, double d[2])
+{
+    if (g->mode == ORACLE_FAN_ARC) {
+        const double gam = s / g->dsd;
+        d[0] = g->dsd * (-cos(gam) * u[0] + sin(gam) * e[0]);
+        d[1] = g->dsd * (-cos(gam) * u[1] + sin(gam) * e[1]);
+    } else {
+        d[0] = -g->dsd * u[0] + s * e[0];
+        d[1] = -g->dsd * u[1] + s * e[1];
+    }
+}
+
 static void make_ray(const oracle_geom *g, int v, int m, ray_frame *r)
 {
     const double th = g->angles[v];
@@ -170,14 +193,17 @@ static void make_ray(const oracle_geom *g, int v, int m, ray_frame *r)
     }
     r->p[0] = g->dsc * u[0];
     r->p[1] = g->dsc * u[1];
-    /* detector point q(s) = p - D_sd u + s e */
-    double d[2] = {-g->dsd * u[0] + s * e[0], -g->dsd * u[1] + s * e[1]};
+    /* detector point q(s) - p: flat, -D_sd u + s e; arc, the point at angle
+     * s / D_sd from -u on the circle of radius D_sd */
+    double d[2];
+    detector_offset(g, u, e, s, d);
     double R = sqrt(d[0] * d[0] + d[1] * d[1]);
     r->w[0] = d[0] / R; r->w[1] = d[1] / R;
     r->wp[0] = -r->w[1]; r->wp[1] = r->w[0];
     for (int side = 0; side < 2; ++side) {
         double se = s + (side ? 0.5 : -0.5) * g->det_width;
-        double qe[2] = {-g->dsd * u[0] + se * e[0], -g->dsd * u[1] + se * e[1]};
+        double qe[2];
+        detector_offset(g, u, e, se, qe);
         double *out = side ? r->edge_hi : r->edge_lo;
         out[0] = r->wp[0] * qe[0] + r->wp[1] * qe[1];
         out[1] = r->w[0] * qe[0] + r->w[1] * qe[1];
@@ -238,12 +264,13 @@ static void candidate_cells(const oracle_geom *g, int v, int i, int j,
         const double y = k[1] + ((c & 2) ? 0.5 : -0.5) * g->pixel;
         const double along = e[0] * x + e[1] * y;
         double s;
-        if (g->mode == ORACLE_PARALLEL) {
+        const double depth = g->dsc - (u[0] * x + u[1] * y);
+        if (g->mode == ORACLE_PARALLEL)
             s = along;
-        } else {
-            const double depth = g->dsc - (u[0] * x + u[1] * y);
+        else if (g->mode == ORACLE_FAN_ARC)
+            s = g->dsd * atan2(along, depth);
+        else
             s = g->dsd * along / depth;
-        }
         if (s < smin) smin = s;
         if (s > smax) smax = s;
     }

@@ -130,3 +130,61 @@ def disk_fan_projection(theta, dsc, dsd, s_m, tau, radius):
         f = 2.0 * np.sqrt(np.maximum(radius * radius - d * d, 0.0))
         total += 0.5 * (x1 - x0) * float(np.dot(_GL_W, f))
     return total / tau
+
+
+# ---- arc detector: cells on the circle of radius dsd around the source; the
+# detector coordinate s is arc length, so the ray of s leaves the central ray
+# (towards -u) at the angle s / dsd ----
+
+def arc_direction(theta, dsc, dsd, s):
+    u, e, p = fan_frame(theta, dsc, dsd)
+    g = s / dsd
+    return -math.cos(g) * u + math.sin(g) * e
+
+
+def arc_chord(theta, dsc, dsd, s, lo, hi):
+    """Exact length of the arc-detector ray through coordinate s inside a box."""
+    u, e, p = fan_frame(theta, dsc, dsd)
+    return line_chord(p, arc_direction(theta, dsc, dsd, s), lo, hi)
+
+
+def arc_corner_shadows(theta, dsc, dsd, lo, hi):
+    """Arc coordinates of the rays through the four corners of a box."""
+    u, e, p = fan_frame(theta, dsc, dsd)
+    out = []
+    for x in (lo[0], hi[0]):
+        for y in (lo[1], hi[1]):
+            c = np.array([x, y])
+            out.append(dsd * math.atan2(e @ c, dsc - u @ c))
+    return out
+
+
+def ref_entry_arc(theta, dsc, dsd, s_m, tau, lo, hi):
+    """Reference projector of the arc detector: (1/tau) * integral over the
+    cell's arc of the exact chord, split at the corner rays."""
+    a, b = s_m - 0.5 * tau, s_m + 0.5 * tau
+    cuts = sorted([a, b] + [c for c in arc_corner_shadows(theta, dsc, dsd, lo, hi) if a < c < b])
+    total = 0.0
+    for x0, x1 in zip(cuts[:-1], cuts[1:]):
+        if x1 <= x0:
+            continue
+        xs = 0.5 * (x1 - x0) * _GL_X + 0.5 * (x1 + x0)
+        f = [arc_chord(theta, dsc, dsd, s, lo, hi) for s in xs]
+        total += 0.5 * (x1 - x0) * float(np.dot(_GL_W, f))
+    return total / tau
+
+
+def disk_arc_projection(dsc, dsd, s_m, tau, radius):
+    """Cell-averaged line integral of the centred unit disk on the arc
+    detector: the ray at angle s / dsd passes at dsc |sin(s / dsd)| from the
+    centre; split at the tangent rays."""
+    a, b = s_m - 0.5 * tau, s_m + 0.5 * tau
+    st = dsd * math.asin(radius / dsc)
+    cuts = sorted([a, b] + [c for c in (-st, st) if a < c < b])
+    total = 0.0
+    for x0, x1 in zip(cuts[:-1], cuts[1:]):
+        xs = 0.5 * (x1 - x0) * _GL_X + 0.5 * (x1 + x0)
+        d = dsc * np.abs(np.sin(xs / dsd))
+        f = 2.0 * np.sqrt(np.maximum(radius * radius - d * d, 0.0))
+        total += 0.5 * (x1 - x0) * float(np.dot(_GL_W, f))
+    return total / tau
