@@ -19,9 +19,11 @@
  * D_sc * (cos t, sin t); the flat detector is perpendicular to that direction
  * at distance D_sd from the source; its axis is (sin t, -cos t) (the
  * projection R_{u perp} = [sin t, -cos t] of Sec. III-B).  Cell m is centred at
- * s_m = (m - (n_det - 1)/2) * det_width on that axis (pitch = width).  Pixel
- * (i, j) of an nx x ny image is centred at ((i - (nx-1)/2) delta,
- * (j - (ny-1)/2) delta): columns run along x, rows along y.
+ * s_m = (m - (n_det - 1)/2) * pitch on that axis, with pitch = det_width for
+ * fp_geometry_create.  Pixel (i, j) of an nx x ny image is centred at
+ * ((i - (nx-1)/2) delta, (j - (ny-1)/2) delta): columns run along x, rows
+ * along y.  fp_geometry_create_desc adds the variants the derivation covers:
+ * an arc detector, parallel beams and a pitch different from the width.
  *
  * Layouts (device memory, FP32, contiguous):
  *     image    [batch][ny][nx]          x fastest
@@ -88,6 +90,55 @@ fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_size,
                              double dist_source_detector, int32_t n_views,
                              const double *view_angles, int32_t n_det,
                              double det_width, fp_geometry **out);
+
+/* Beam and detector shapes of fp_geometry_create_desc. */
+typedef enum {
+    /* fan beam, flat detector: as fp_geometry_create */
+    FP_FAN_FLAT = 0,
+    /* fan beam, arc detector: the cells lie on the circle of radius D_sd
+     * around the source and s is arc length on it, so the ray of cell m
+     * leaves the central ray (from the source through the centre) at the
+     * angle s_m / D_sd, towards +(sin t, -cos t) for s_m > 0; the cell's two
+     * edges are the points at s_m -/+ width/2 on the arc.  The paper notes
+     * the arc detector as a special case of its flat-detector derivation
+     * (Sec. I); eq. (13), (16)-(18) are applied to that ray and those edges,
+     * which gives tau' = L * 2 tan(width / (2 D_sd)). */
+    FP_FAN_ARC = 1,
+    /* parallel beam: every ray of view t runs along -(cos t, sin t); the ray
+     * of cell m is the line (sin t, -cos t) . x = s_m and tau' = width, for
+     * which the model is exact (Theorem 1).  The two distances are ignored. */
+    FP_PARALLEL = 2
+} fp_beam;
+
+/* Full geometry description for fp_geometry_create_desc.  Fields as for
+ * fp_geometry_create, plus:
+ *   beam       an fp_beam value
+ *   det_pitch  distance between neighbouring cell centres (> 0); cells may
+ *              overlap (width > pitch) or leave gaps (width < pitch), the
+ *              separate spacing and width of Sec. V
+ *   det_width  the width tau of one cell's aperture (> 0)
+ * For FP_PARALLEL, dist_source_center and dist_source_detector are not read.
+ * For FP_FAN_ARC, the outermost cell edge must stay within 80 degrees of the
+ * central ray: (n_det/2) * det_pitch + det_width/2 < 1.396 * D_sd. */
+typedef struct {
+    int32_t beam;
+    int32_t nx, ny;
+    double pixel_size;
+    double dist_source_center;
+    double dist_source_detector;
+    int32_t n_views;
+    const double *view_angles;   /* host, n_views finite radians, copied */
+    int32_t n_det;
+    double det_pitch;
+    double det_width;
+} fp_geometry_desc;
+
+/* Create a geometry from a description; otherwise exactly as
+ * fp_geometry_create (same validation, errors, ownership and
+ * synchronisation).  fp_geometry_create(...) is fp_geometry_create_desc with
+ * beam = FP_FAN_FLAT and det_pitch = det_width.  Every other entry point
+ * accepts a geometry of any beam. */
+fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_geometry **out);
 
 /* Free the geometry's device tables (synchronises the device).  NULL is a
  * no-op.  The geometry must not be in use by queued work. */

@@ -1,21 +1,28 @@
 """Build libfanproj.so in-tree with hipcc for gfx950.
 
     python -m paper_1907_10526_amd.build
+
+Each source compiles to an object in parallel (the back-projection kernels of
+the three beam shapes sit in separate files for that), then one link step.
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfanproj.so")
-SOURCES = ["projector.hip", "tables.hip", "geometry.cpp", "abi.cpp"]
+SOURCES = ["forward.hip", "back_flat_f32.hip", "back_flat_f64.hip", "back_arc_f32.hip", "back_arc_f64.hip",
+           "back_parallel_f32.hip", "back_parallel_f64.hip", "back.cpp",
+           "multi.hip", "tables.hip", "geometry.cpp", "abi.cpp"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # every value the kernels handle is finite and the sign of a zero never
@@ -25,18 +32,34 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfanproj.so")
-    os.replace(tmp, OUT)
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="fanproj_build_") as tmpdir:
+        def compile_one(src):
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+                   os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            return obj, subprocess.run(cmd, capture_output=True, text=True)
+
+        with ThreadPoolExecutor(max_workers=jobs) as pool:
+            results = list(pool.map(compile_one, SOURCES))
+        failed = [(src, r) for src, (_, r) in zip(SOURCES, results) if r.returncode != 0]
+        for src, r in failed:
+            sys.stderr.write(f"--- {src}\n{r.stdout}{r.stderr}")
+        if failed:
+            raise RuntimeError("hipcc failed compiling " + ", ".join(src for src, _ in failed))
+        tmp = OUT + ".tmp"
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in results], "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libfanproj.so")
+        os.replace(tmp, OUT)
     return OUT
 
 

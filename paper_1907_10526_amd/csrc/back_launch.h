@@ -1,0 +1,88 @@
+// Back projection launchers for one beam shape: the batch-chunk, LDS
+// capacity and mode dispatch down to one back_kernel instantiation.  Each
+// beam and precision has a translation unit (back_<beam>_<f32/f64>.hip) that
+// includes this and instantiates launch_back_beam for its beam, so the
+// kernels of the three shapes compile in parallel.
+#pragma once
+
+#include "kernels.h"
+
+namespace fanproj {
+namespace {
+
+template <typename Real, int NB, int CAP>
+constexpr bool back_fits() {
+    return 2 * (size_t)(kBackRayParams + NB) * CAP * sizeof(Real) <= kBackLdsLimit;
+}
+
+template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
+hipError_t launch_back_t(const DevGeom &g, const Real *sino, Real *img, Real *partial,
+                         const Real *col_w, Real relaxation, hipStream_t stream) {
+    if constexpr (!back_fits<Real, NB, CAP>()) {
+        return hipErrorInvalidValue;  // excluded by back_max_batch
+    } else {
+        const int groups = partial ? g.back_groups : 1;
+        dim3 grid(g.tiles_x, g.tiles_y, groups);
+        hipLaunchKernelGGL((back_kernel<Real, NB, CAP, MODE, BEAM>), grid, dim3(kBackThreads), 0,
+                           stream, g, sino, img, partial, col_w, relaxation);
+        if (groups > 1) {
+            const size_t npix = (size_t)g.nx * g.ny;
+            const unsigned blocks = (unsigned)std::min<size_t>((npix + 255) / 256, 4096);
+            hipLaunchKernelGGL((back_finalize_kernel<Real, NB, MODE>), dim3(blocks), dim3(256), 0,
+                               stream, partial, groups, npix, img, col_w, relaxation);
+        }
+        return hipGetLastError();
+    }
+}
+
+template <typename Real, int NB, BackMode MODE, int BEAM>
+hipError_t launch_back_cap(const DevGeom &g, const Real *sino, Real *img, Real *partial,
+                           const Real *col_w, Real relaxation, hipStream_t stream) {
+    switch (g.back_cap) {
+        case 64: return launch_back_t<Real, NB, 64, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 128: return launch_back_t<Real, NB, 128, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 256: return launch_back_t<Real, NB, 256, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 512: return launch_back_t<Real, NB, 512, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 1024: return launch_back_t<Real, NB, 1024, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename Real, BackMode MODE, int BEAM>
+hipError_t launch_back_nb(const DevGeom &g, int nb, const Real *sino, Real *img, Real *partial,
+                          const Real *col_w, Real relaxation, hipStream_t stream) {
+    switch (nb) {
+        case 1: return launch_back_cap<Real, 1, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 2: return launch_back_cap<Real, 2, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 4: return launch_back_cap<Real, 4, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 8: return launch_back_cap<Real, 8, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+template <typename Real, int BEAM>
+hipError_t launch_back_beam(const DevGeom &g, BackMode mode, int nb, const Real *sino, Real *img,
+                            Real *partial, const Real *col_w, Real relaxation,
+                            hipStream_t stream) {
+    switch (mode) {
+        case BackMode::kPlain:
+            return launch_back_nb<Real, BackMode::kPlain, BEAM>(g, nb, sino, img, partial, col_w,
+                                                                relaxation, stream);
+        case BackMode::kSirtUpdate:
+            return launch_back_nb<Real, BackMode::kSirtUpdate, BEAM>(g, nb, sino, img, partial,
+                                                                     col_w, relaxation, stream);
+        case BackMode::kOnes:
+            return launch_back_cap<Real, 1, BackMode::kOnes, BEAM>(g, sino, img, partial, col_w,
+                                                                   relaxation, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fanproj
+
+#define FANPROJ_INSTANTIATE_BACK(Real, BEAM)                                                      \
+    template hipError_t fanproj::launch_back_beam<Real, BEAM>(                                    \
+        const fanproj::DevGeom &, fanproj::BackMode, int, const Real *, Real *, Real *,           \
+        const Real *, Real, hipStream_t);

@@ -72,11 +72,23 @@ struct DevGeom {
     int max_cells;           // largest per-(view, tile) cell range
     int back_cap;            // LDS capacity (cells) of the back kernel in use
     int back_groups;         // view groups of the back projection (>= 1)
+    int beam;                // FP_FAN_FLAT, FP_FAN_ARC or FP_PARALLEL
     double pixel;            // delta
     double dsc, dsd;         // source-centre, source-detector distances
-    double tau;              // cell width (= pitch)
+    double tau;              // cell width (aperture)
+    double pitch;            // distance between cell centres
+    // Cell spacing in the coordinate the back projection places windows in:
+    // the pitch (flat: detector coordinate; parallel: e.x), or the angle
+    // pitch / D_sd (arc).
+    double cell_step;
     double half_diag;        // radius of a disk containing every pixel
     const double2 *views;    // [nv] (cos t, sin t)
+    // arc detector only: (cos g_m, sin g_m), g_m = s_m / D_sd, for cells
+    // m = -kBackPad .. nd + kBackPad - 1 at index m + kBackPad; and
+    // (cos, sin) of t * (pitch / D_sd) for t < kBackMaxUnrolled
+    const double2 *arc_cells;
+    const float2 *arc_rot;
+    const double2 *arc_rot64;
     RayTables<float> r32;
     RayTables<double> r64;   // built on the first FP64 call
     // [nv][tiles_y * tiles_x]: first cell M0 and count of the cells the tile
@@ -87,6 +99,21 @@ struct DevGeom {
 
 template <typename Real>
 __host__ __device__ inline const RayTables<Real> &ray_tables(const DevGeom &g);
+// The arc rotations in the kernels' arithmetic type, as (cos, sin) pairs.
+template <typename Real>
+__device__ inline void arc_rotation(const DevGeom &g, int t, Real &c, Real &s);
+template <>
+__device__ inline void arc_rotation<float>(const DevGeom &g, int t, float &c, float &s) {
+    const float2 r = g.arc_rot[t];
+    c = r.x;
+    s = r.y;
+}
+template <>
+__device__ inline void arc_rotation<double>(const DevGeom &g, int t, double &c, double &s) {
+    const double2 r = g.arc_rot64[t];
+    c = r.x;
+    s = r.y;
+}
 template <>
 __host__ __device__ inline const RayTables<float> &ray_tables<float>(const DevGeom &g) {
     return g.r32;
@@ -99,7 +126,8 @@ __host__ __device__ inline const RayTables<double> &ray_tables<double>(const Dev
 enum class FwdMode : int { kPlain = 0, kSirtResidual = 1, kOnes = 2, kCount = 3 };
 enum class BackMode : int { kPlain = 0, kSirtUpdate = 1, kOnes = 2 };
 
-// Kernel launchers (projector.hip), instantiated for Real = float and double.
+// Kernel launchers (forward.hip, back*.hip / back.cpp), instantiated for
+// Real = float and double.
 // Return the hipError_t of the launch.
 // launch_forward: `img` is the caller's [nb][ny][nx] image (unused by the
 // kOnes / kCount modes); `work` is device scratch of forward_work_bytes
@@ -117,6 +145,11 @@ hipError_t launch_back(const DevGeom &g, BackMode mode, int nb, const Real *sino
                        Real *partial, const Real *col_w, Real relaxation, hipStream_t stream);
 template <typename Real>
 size_t back_work_bytes(const DevGeom &g, int nb);
+// launch_back for one beam shape (BEAM = FP_FAN_FLAT, FP_FAN_ARC or
+// FP_PARALLEL); launch_back dispatches on g.beam.
+template <typename Real, int BEAM>
+hipError_t launch_back_beam(const DevGeom &g, BackMode mode, int nb, const Real *sino, Real *img,
+                            Real *partial, const Real *col_w, Real relaxation, hipStream_t stream);
 // Largest batch chunk the back kernel's LDS holds for this geometry (0 if
 // even one image does not fit).
 template <typename Real>
@@ -144,16 +177,16 @@ struct MultiArgs {
     MultiJob job[kMaxJobsPerLaunch];
 };
 static_assert(sizeof(MultiArgs) <= 4000, "kernel arguments must stay under 4 KB");
-// Launch the three phases for args.job[0 .. n); rows/cols/fwd_begin/
-// back_begin must be filled in.
+// Launch the three phases for args.job[0 .. n) (multi.hip); rows/cols/
+// fwd_begin/back_begin must be filled in.
 hipError_t launch_sirt_multi(const MultiArgs &args, hipStream_t stream);
 
 }  // namespace fanproj
 
 struct fp_geometry {
     int device = 0;
-    int nx = 0, ny = 0, nv = 0, nd = 0;
-    double pixel = 0, dsc = 0, dsd = 0, tau = 0;
+    int nx = 0, ny = 0, nv = 0, nd = 0, beam = FP_FAN_FLAT;
+    double pixel = 0, dsc = 0, dsd = 0, tau = 0, pitch = 0;
     std::vector<double> angles;
     fanproj::DevGeom dev{};
     void *table_block = nullptr;   // one device allocation for the FP32 tables

@@ -1,0 +1,82 @@
+// Forward projection: launchers of the padded image copies and of the
+// ray-driven forward kernel (instantiated for FP32 and FP64).
+#include "kernels.h"
+
+namespace fanproj {
+namespace {
+
+template <typename Real, int NB, FwdMode MODE>
+hipError_t launch_fwd_t(const DevGeom &g, const Real *img, Real *work, Real *out, int *counts,
+                        const Real *y_meas, const Real *row_w, hipStream_t stream) {
+    const Real *rows = nullptr, *cols = nullptr;
+    if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
+        const int nrows = std::max(g.nx, g.ny);
+        Real *wr = work;
+        Real *wc = work + (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
+        const size_t total = (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
+        const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
+        hipLaunchKernelGGL(pad_rows_kernel<Real>, dim3(blocks), dim3(256), 0, stream, img, wr, g.nx,
+                           g.ny, nrows, NB);
+        dim3 tgrid((nrows + 31) / 32, (g.ny + 2 * kFwdPad + 31) / 32, NB);
+        hipLaunchKernelGGL(pad_cols_kernel<Real>, tgrid, dim3(32, 8), 0, stream, img, wc, g.nx,
+                           g.ny, nrows);
+        rows = wr;
+        cols = wc;
+    }
+    dim3 grid((g.nd + kFwdThreads - 1) / kFwdThreads, g.nv);
+    hipLaunchKernelGGL((forward_kernel<Real, NB, MODE>), grid, dim3(kFwdThreads), 0, stream, g,
+                       rows, cols, out, counts, y_meas, row_w);
+    return hipGetLastError();
+}
+
+template <typename Real, FwdMode MODE>
+hipError_t launch_fwd_nb(const DevGeom &g, int nb, const Real *img, Real *work, Real *out,
+                         int *counts, const Real *y_meas, const Real *row_w, hipStream_t stream) {
+    switch (nb) {
+        case 1: return launch_fwd_t<Real, 1, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        case 2: return launch_fwd_t<Real, 2, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        case 4: return launch_fwd_t<Real, 4, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        case 8: return launch_fwd_t<Real, 8, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+template <typename Real>
+size_t forward_work_bytes(const DevGeom &g, int nb) {
+    const size_t nrows = (size_t)std::max(g.nx, g.ny);
+    return (size_t)nb * sizeof(Real) * nrows * ((size_t)(g.nx + 2 * kFwdPad) + (g.ny + 2 * kFwdPad));
+}
+
+template <typename Real>
+hipError_t launch_forward(const DevGeom &g, FwdMode mode, int nb, const Real *img, Real *work,
+                          Real *out, int *counts, const Real *y_meas, const Real *row_w,
+                          hipStream_t stream) {
+    switch (mode) {
+        case FwdMode::kPlain:
+            return launch_fwd_nb<Real, FwdMode::kPlain>(g, nb, img, work, out, counts, y_meas,
+                                                        row_w, stream);
+        case FwdMode::kSirtResidual:
+            return launch_fwd_nb<Real, FwdMode::kSirtResidual>(g, nb, img, work, out, counts,
+                                                               y_meas, row_w, stream);
+        case FwdMode::kOnes:
+            return launch_fwd_t<Real, 1, FwdMode::kOnes>(g, img, work, out, counts, y_meas, row_w,
+                                                         stream);
+        case FwdMode::kCount:
+            return launch_fwd_t<Real, 1, FwdMode::kCount>(g, img, work, out, counts, y_meas, row_w,
+                                                          stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+#define FANPROJ_INSTANTIATE(Real)                                                                  \
+    template size_t forward_work_bytes<Real>(const DevGeom &, int);                                \
+    template hipError_t launch_forward<Real>(const DevGeom &, FwdMode, int, const Real *, Real *,  \
+                                             Real *, int *, const Real *, const Real *,            \
+                                             hipStream_t);
+FANPROJ_INSTANTIATE(float)
+FANPROJ_INSTANTIATE(double)
+#undef FANPROJ_INSTANTIATE
+
+}  // namespace fanproj

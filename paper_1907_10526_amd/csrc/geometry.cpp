@@ -34,7 +34,8 @@ fp_status ensure_f64_tables(fp_geometry *g) {
     }
     char *base = static_cast<char *>(g->f64_block);
     RayTableArgs ra{};
-    ra.nv = g->nv; ra.nd = g->nd; ra.dsd = g->dsd; ra.tau = g->tau; ra.pixel = g->pixel;
+    ra.nv = g->nv; ra.nd = g->nd; ra.beam = g->beam;
+    ra.dsd = g->dsd; ra.pitch = g->pitch; ra.width = g->tau; ra.pixel = g->pixel;
     for (int k = 0; k < kRayTables; ++k) ra.f64[k] = reinterpret_cast<double *>(base + k * per);
     e = launch_ray_tables(g->dev.views, ra, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -58,26 +59,60 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
                                         double dist_source_detector, int32_t n_views,
                                         const double *view_angles, int32_t n_det,
                                         double det_width, fp_geometry **out) {
+    fp_geometry_desc d{};
+    d.beam = FP_FAN_FLAT;
+    d.nx = nx; d.ny = ny; d.pixel_size = pixel_size;
+    d.dist_source_center = dist_source_center; d.dist_source_detector = dist_source_detector;
+    d.n_views = n_views; d.view_angles = view_angles;
+    d.n_det = n_det; d.det_pitch = det_width; d.det_width = det_width;
+    return fp_geometry_create_desc(&d, out);
+}
+
+extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_geometry **out) {
     clear_error();
     if (!out) { set_error("fp_geometry_create: out is NULL"); return FP_ERR_INVALID_ARG; }
+    if (!desc) { set_error("fp_geometry_create: desc is NULL"); return FP_ERR_INVALID_ARG; }
+    const int beam = desc->beam;
+    const int32_t nx = desc->nx, ny = desc->ny, n_views = desc->n_views, n_det = desc->n_det;
+    const double pixel_size = desc->pixel_size, det_width = desc->det_width, pitch = desc->det_pitch;
+    const double *view_angles = desc->view_angles;
+    const bool fan = beam != FP_PARALLEL;
+    // parallel beams have no source: the distances are not read
+    const double dist_source_center = fan ? desc->dist_source_center : 0.0;
+    const double dist_source_detector = fan ? desc->dist_source_detector : 0.0;
+    if (beam != FP_FAN_FLAT && beam != FP_FAN_ARC && beam != FP_PARALLEL) {
+        set_error("fp_geometry_create: unknown beam " + std::to_string(beam));
+        return FP_ERR_INVALID_ARG;
+    }
     if (!view_angles) { set_error("fp_geometry_create: view_angles is NULL"); return FP_ERR_INVALID_ARG; }
     if (nx < 1 || ny < 1 || n_views < 1 || n_det < 1) {
         set_error("fp_geometry_create: nx, ny, n_views and n_det must be >= 1");
         return FP_ERR_INVALID_ARG;
     }
-    if (!finite_positive(pixel_size) || !finite_positive(det_width) ||
-        !finite_positive(dist_source_center) || !std::isfinite(dist_source_detector)) {
-        set_error("fp_geometry_create: pixel_size, det_width and the distances must be finite and > 0");
-        return FP_ERR_INVALID_ARG;
-    }
-    if (!(dist_source_detector > dist_source_center)) {
-        set_error("fp_geometry_create: dist_source_detector must exceed dist_source_center");
+    if (!finite_positive(pixel_size) || !finite_positive(det_width) || !finite_positive(pitch)) {
+        set_error("fp_geometry_create: pixel_size, det_width and the pitch must be finite and > 0");
         return FP_ERR_INVALID_ARG;
     }
     const double half_diag = pixel_size * 0.5 * std::sqrt((double)nx * nx + (double)ny * ny);
-    if (!(dist_source_center > half_diag + pixel_size)) {
-        set_error("fp_geometry_create: the source must lie outside the image "
-                  "(dist_source_center > pixel_size * (sqrt(nx^2+ny^2)/2 + 1))");
+    if (fan) {
+        if (!finite_positive(dist_source_center) || !std::isfinite(dist_source_detector)) {
+            set_error("fp_geometry_create: the distances must be finite and > 0");
+            return FP_ERR_INVALID_ARG;
+        }
+        if (!(dist_source_detector > dist_source_center)) {
+            set_error("fp_geometry_create: dist_source_detector must exceed dist_source_center");
+            return FP_ERR_INVALID_ARG;
+        }
+        if (!(dist_source_center > half_diag + pixel_size)) {
+            set_error("fp_geometry_create: the source must lie outside the image "
+                      "(dist_source_center > pixel_size * (sqrt(nx^2+ny^2)/2 + 1))");
+            return FP_ERR_INVALID_ARG;
+        }
+    }
+    if (beam == FP_FAN_ARC &&
+        !(0.5 * n_det * pitch + 0.5 * det_width < 80.0 * M_PI / 180.0 * dist_source_detector)) {
+        set_error("fp_geometry_create: the arc detector must stay within 80 degrees of the "
+                  "central ray ((n_det/2) * det_pitch + det_width/2 < 1.396 * dist_source_detector)");
         return FP_ERR_INVALID_ARG;
     }
     for (int v = 0; v < n_views; ++v)
@@ -93,9 +128,10 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     auto g = std::make_unique<fp_geometry>();
     hipError_t e = hipGetDevice(&g->device);
     if (e != hipSuccess) return device_error("hipGetDevice", e);
-    g->nx = nx; g->ny = ny; g->nv = n_views; g->nd = n_det;
+    g->nx = nx; g->ny = ny; g->nv = n_views; g->nd = n_det; g->beam = beam;
     g->pixel = pixel_size; g->dsc = dist_source_center; g->dsd = dist_source_detector;
     g->tau = det_width;
+    g->pitch = pitch;
     g->angles.assign(view_angles, view_angles + n_views);
 
     const size_t nr = (size_t)n_views * n_det;
@@ -111,24 +147,33 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     }
     const double D = dist_source_detector, tau = det_width, delta = pixel_size;
     const double c0 = 0.5 * (n_det - 1);
-    // Largest half effective blur anywhere: tau'/2 = g_m L / 2 with
-    // L <= D_sc D / R_m + (radius of the image) <= D_sc + half_diag + delta.
-    double gmax = 0.0;
-    for (int m = 0; m < n_det; ++m) {
-        const double s = (m - c0) * tau;
-        gmax = std::max(gmax, 0.5 * tau * D *
-                                  (1.0 / (D * D + s * (s + 0.5 * tau)) +
-                                   1.0 / (D * D + s * (s - 0.5 * tau))));
+    // Largest half effective blur anywhere: tau'/2 = g L / 2 with
+    // L <= D_sc + (radius of the image) (fan), or tau / 2 (parallel).
+    double hc_max = 0.5 * tau;
+    if (beam == FP_FAN_FLAT) {
+        double gmax = 0.0;
+        for (int m = 0; m < n_det; ++m) {
+            const double s = (m - c0) * pitch;
+            gmax = std::max(gmax, 0.5 * tau * D *
+                                      (1.0 / (D * D + s * (s + 0.5 * tau)) +
+                                       1.0 / (D * D + s * (s - 0.5 * tau))));
+        }
+        hc_max = 0.5 * gmax * (dist_source_center + half_diag + delta);
+    } else if (beam == FP_FAN_ARC) {
+        hc_max = std::tan(0.5 * tau / D) * (dist_source_center + half_diag + delta);
     }
-    const double hc_max = 0.5 * gmax * (dist_source_center + half_diag + delta);
 
-    // ---- device block: views, per-ray tables, per-tile table, two maxima ----
+    // ---- device block: views, per-ray tables, per-tile table, arc cells, two maxima ----
     const size_t A = 256;
+    const size_t n_arc = beam == FP_FAN_ARC ? (size_t)n_det + 2 * kBackPad : 0;
     size_t off = 0;
     const size_t off_views = off; off = align_up(off + views.size() * sizeof(double), A);
     size_t off_rays[kRayTables];
     for (int k = 0; k < kRayTables; ++k) { off_rays[k] = off; off = align_up(off + nr * sizeof(float), A); }
     const size_t off_tiles = off; off = align_up(off + (size_t)n_views * ntiles * sizeof(int4), A);
+    const size_t off_arc = off; off = align_up(off + n_arc * sizeof(double2), A);
+    const size_t off_rot = off; off = align_up(off + (n_arc ? kBackMaxUnrolled : 0) * sizeof(float2), A);
+    const size_t off_rot64 = off; off = align_up(off + (n_arc ? kBackMaxUnrolled : 0) * sizeof(double2), A);
     const size_t off_max = off; off = align_up(off + 2 * sizeof(int), A);
     g->table_bytes = off;
     e = hipMalloc(&g->table_block, g->table_bytes);
@@ -151,17 +196,27 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     if (e != hipSuccess) return fail("fp_geometry_create: hipMemset", e);
     const double2 *d_views = reinterpret_cast<const double2 *>(base + off_views);
     RayTableArgs ra{};
-    ra.nv = n_views; ra.nd = n_det; ra.dsd = D; ra.tau = tau; ra.pixel = delta;
+    ra.nv = n_views; ra.nd = n_det; ra.beam = beam;
+    ra.dsd = D; ra.pitch = pitch; ra.width = tau; ra.pixel = delta;
     for (int k = 0; k < kRayTables; ++k) ra.f32[k] = reinterpret_cast<float *>(base + off_rays[k]);
     e = launch_ray_tables(d_views, ra, nullptr);
     if (e != hipSuccess) return fail("fp_geometry_create: ray tables", e);
     TileTableArgs ta{};
     ta.nx = nx; ta.ny = ny; ta.nv = n_views; ta.nd = n_det; ta.tiles_x = tiles_x; ta.tiles_y = tiles_y;
-    ta.pixel = delta; ta.dsc = dist_source_center; ta.dsd = D; ta.tau = tau; ta.hc_max = hc_max;
+    ta.beam = beam;
+    ta.pixel = delta; ta.dsc = dist_source_center; ta.dsd = D; ta.pitch = pitch; ta.width = tau;
+    ta.hc_max = hc_max;
     int4 *d_tiles = reinterpret_cast<int4 *>(base + off_tiles);
     int *d_max = reinterpret_cast<int *>(base + off_max);
     e = launch_tile_table(d_views, ta, d_tiles, d_max, nullptr);
     if (e != hipSuccess) return fail("fp_geometry_create: tile table", e);
+    double2 *d_arc = n_arc ? reinterpret_cast<double2 *>(base + off_arc) : nullptr;
+    float2 *d_rot = n_arc ? reinterpret_cast<float2 *>(base + off_rot) : nullptr;
+    double2 *d_rot64 = n_arc ? reinterpret_cast<double2 *>(base + off_rot64) : nullptr;
+    if (d_arc) {
+        e = launch_arc_cells(n_det, pitch, D, d_arc, d_rot, d_rot64, nullptr);
+        if (e != hipSuccess) return fail("fp_geometry_create: arc cells", e);
+    }
     int maxima[2] = {0, 0};
     e = hipMemcpy(maxima, d_max, sizeof(maxima), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail("fp_geometry_create: tables", e);
@@ -171,9 +226,14 @@ extern "C" fp_status fp_geometry_create(int32_t nx, int32_t ny, double pixel_siz
     d.nx = nx; d.ny = ny; d.nv = n_views; d.nd = n_det;
     d.tiles_x = tiles_x; d.tiles_y = tiles_y;
     d.max_cells = max_cells;
-    d.pixel = delta; d.dsc = dist_source_center; d.dsd = D; d.tau = tau;
+    d.beam = beam;
+    d.pixel = delta; d.dsc = dist_source_center; d.dsd = D; d.tau = tau; d.pitch = pitch;
+    d.cell_step = beam == FP_FAN_ARC ? pitch / D : pitch;
     d.half_diag = half_diag + delta;
     d.views = d_views;
+    d.arc_cells = d_arc;
+    d.arc_rot = d_rot;
+    d.arc_rot64 = d_rot64;
     d.r32 = RayTables<float>{ra.f32[0], ra.f32[1], ra.f32[2], ra.f32[3], ra.f32[4], ra.f32[5], ra.f32[6]};
     d.r64 = RayTables<double>{};
     d.tile_cells = d_tiles;

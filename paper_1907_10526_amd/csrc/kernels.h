@@ -1,4 +1,5 @@
-// CNSF forward and back projection kernels for gfx950 (MI355X).
+// CNSF forward and back projection kernels for gfx950 (MI355X): the device
+// code shared by the translation units that instantiate and launch it.
 //
 // Every matrix entry is evaluated on the fly (Sec. V-C: no stored system
 // matrix, no look-up table) as the closed form of eq. (18):
@@ -43,6 +44,8 @@
 // relative.  Every kernel is instantiated for Real = float (the production
 // path) and Real = double (the same arithmetic in FP64 with FP64 tables, for
 // finite-difference and adjoint checks).
+#pragma once
+
 #include <algorithm>
 
 #include "fanproj_internal.h"
@@ -291,19 +294,46 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     // ---- per-ray frame in FP64 (Sec. II-A, eq. (13)) ----
     const double2 cs = G.views[v];
     const double c = cs.x, sn = cs.y, D = G.dsd;
-    const double s = (m - 0.5 * (G.nd - 1)) * G.tau;
-    const double R = sqrt(D * D + s * s);
-    const double invR = 1.0 / R;
-    // ray direction w = (-D u + s e) / R, u = (c, sn), e = (sn, -c);
-    // normal w_perp = w rotated by +90 degrees.
-    const double wx = (-D * c + s * sn) * invR;
-    const double wy = (-D * sn - s * c) * invR;
-    const double wpx = -wy, wpy = wx;
-    const double px = G.dsc * c, py = G.dsc * sn;
+    const double s = (m - 0.5 * (G.nd - 1)) * G.pitch;
     const double x0 = -0.5 * (G.nx - 1) * G.pixel, y0 = -0.5 * (G.ny - 1) * G.pixel;
-    // s'(i, j) and L(i, j) are affine in the pixel indices.
-    const double S00 = wpx * (x0 - px) + wpy * (y0 - py);
-    const double L00 = wx * (x0 - px) + wy * (y0 - py);
+    // ray direction w (source towards detector) and normal w_perp = w rotated
+    // by +90 degrees; s'(i, j) and L(i, j) are affine in the pixel indices;
+    // the half effective blur is hc = hc_fix + gR * L (eq. (17))
+    double wx, wy, S00, L00, gR, hc_fix, lmax;
+    if (G.beam == FP_PARALLEL) {
+        // every ray runs along -u; s' = e.k - s_m, tau' = tau
+        wx = -c;
+        wy = -sn;
+        S00 = sn * x0 - c * y0 - s;
+        L00 = 0.0;
+        gR = 0.0;
+        hc_fix = 0.5 * G.tau;
+        lmax = 0.0;
+    } else {
+        // the ray leaves the central ray (-u) at angle g towards e:
+        // w = -cos g u + sin g e, e = (sn, -c)
+        double cg, sg;
+        if (G.beam == FP_FAN_ARC) {
+            const double2 a = G.arc_cells[m + kBackPad];
+            cg = a.x;
+            sg = a.y;
+            gR = (double)tab.ghr[ray];                  // tan(tau / (2 D))
+        } else {
+            const double R = sqrt(D * D + s * s);
+            cg = D / R;
+            sg = s / R;
+            gR = (double)tab.ghr[ray] * R;              // g_m / 2
+        }
+        wx = -cg * c + sg * sn;
+        wy = -cg * sn - sg * c;
+        const double px = G.dsc * c, py = G.dsc * sn;
+        S00 = -wy * (x0 - px) + wx * (y0 - py);
+        L00 = wx * (x0 - px) + wy * (y0 - py);
+        hc_fix = 0.0;
+        // depth of the far side of the disk containing the image
+        lmax = G.dsc * cg + G.half_diag;
+    }
+    const double wpx = -wy, wpy = wx;
     // March along the image axis closest to the ray; the other ("cross")
     // axis then advances s' by at least delta / sqrt(2) per pixel.
     const bool by_rows = fabs(wy) >= fabs(wx);
@@ -318,8 +348,6 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     w.trap.ia = tab.ia[ray];
     w.trap.nhbia = tab.nhbia[ray];
     w.trap.ha = tab.ha[ray];
-    // half effective blur hc = tau'/2 = ghr * R * L, affine in (q, r)
-    const double gR = (double)tab.ghr[ray] * R;
     w.dhq = (Real)(gR * lc);
     w.dhr = (Real)(gR * lm);
     w.zcr = (Real)w.zc;
@@ -331,8 +359,7 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 
     // Support |s'| < hab + hc, with hc bounded by its value at the far side
     // of the disk containing the image.
-    const double lmax = G.dsc * D * invR + G.half_diag;
-    const double hw = (double)w.trap.hab + gR * lmax;
+    const double hw = (double)w.trap.hab + hc_fix + gR * lmax;
     w.izc = 1.0 / w.zc;
     w.hq = hw * fabs(w.izc);
     const int T = (int)floor(2.0 * w.hq) + 1;   // pixels per row that can be hit
@@ -360,7 +387,7 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     const int r1 = wave_max(r_hi);
     r0 = max(r0, 0);
     w.S = S00 + r0 * w.zm;
-    w.hcr = (Real)(gR * (L00 + r0 * lm));
+    w.hcr = (Real)(hc_fix + gR * (L00 + r0 * lm));
 
     Real acc[NB];
 #pragma unroll
@@ -517,13 +544,56 @@ __device__ __forceinline__ void back_window(const BackLds<Real, NB, CAP> &l, int
     }
 }
 
+// Arc detector: entries of one pixel with cells w0 .. w0 + T - 1 of the
+// staged arrays (cell m = m_first + t).  s' = rho sin(g_k - g_m) and
+// L = rho cos(g_k - g_m), with rho and g_k the distance and angle of the
+// pixel centre from the source.  Unrolled: a0 and b0 are s' and L at the
+// first cell, and cell t is their rotation by t times the angular pitch.
+// Wide windows: s' = cos g_m (e.k) - sin g_m h and L = cos g_m h + sin g_m (e.k)
+// per cell in FP64.
+template <typename Real, int NB, int CAP, bool UNROLLED>
+__device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l, const DevGeom &G,
+                                                int w0, int T, int m_first, double ek, double h,
+                                                Real (&part)[NB]) {
+    const Real *ghr = l.ghr + w0;
+    const Real *hab = l.hab + w0;
+    const Real *ia = l.ia + w0;
+    const Real *nhbia = l.nhbia + w0;
+    const Real *ha = l.ha + w0;
+    auto entry = [&](int t, Real sp, Real L) {
+        const Real hc = L * ghr[t];
+        const Trap<Real> p{hab[t], ia[t], nhbia[t], ha[t]};
+        const Real e = footprint_num(sp, hc, p) * fast_rcp(hc);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) part[b] = fma(e, l.w[b][w0 + t], part[b]);
+    };
+    const double2 *cells = G.arc_cells + m_first + kBackPad;
+    if constexpr (UNROLLED) {
+        const double2 g = cells[0];
+        const Real a0 = (Real)(g.x * ek - g.y * h);
+        const Real b0 = (Real)(g.x * h + g.y * ek);
+#pragma unroll
+        for (int t = 0; t < kBackMaxUnrolled; ++t) {
+            if (t >= T) break;  // T is uniform across the work-group
+            Real rc, rs;
+            arc_rotation<Real>(G, t, rc, rs);
+            entry(t, fma(-b0, rs, a0 * rc), fma(a0, rs, b0 * rc));
+        }
+    } else {
+        for (int t = 0; t < T; ++t) {
+            const double2 g = cells[t];
+            entry(t, (Real)(g.x * ek - g.y * h), (Real)(g.x * h + g.y * ek));
+        }
+    }
+}
+
 // One tile (tx, ty) and view group `group` of `groups`.
-template <typename Real, int NB, int CAP, BackMode MODE>
-__device__ __forceinline__ void back_block(const DevGeom &G, int tx, int ty, int group, int groups,
+template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
+__device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], const DevGeom &G,
+                                           int tx, int ty, int group, int groups,
                                            const Real *__restrict__ sino, Real *__restrict__ img,
                                            Real *__restrict__ partial,
                                            const Real *__restrict__ col_w, Real relaxation) {
-    __shared__ BackLds<Real, NB, CAP> lds[2];
     const RayTables<Real> &tab = ray_tables<Real>(G);
 
     const int tile = ty * G.tiles_x + tx;
@@ -542,9 +612,9 @@ __device__ __forceinline__ void back_block(const DevGeom &G, int tx, int ty, int
     const double xk = (i - 0.5 * (G.nx - 1)) * G.pixel;
     const double yk0 = (j0 - 0.5 * (G.ny - 1)) * G.pixel;
     const double ystep = kRowStep * G.pixel;
-    const double D = G.dsd, tau = G.tau, c0 = 0.5 * (G.nd - 1);
-    const Real Dr = (Real)D, taur = (Real)tau;
-    const float itau = (float)(1.0 / tau), c0f = (float)c0;
+    const double D = G.dsd, step = G.cell_step, c0 = 0.5 * (G.nd - 1);
+    const Real Dr = (Real)D, stepr = (Real)step;
+    const float istep = (float)(1.0 / step), c0f = (float)c0;
 
     Real acc[P][NB];
 #pragma unroll
@@ -583,30 +653,56 @@ __device__ __forceinline__ void back_block(const DevGeom &G, int tx, int ty, int
                 const double dek = -ystep * cs.x, dh = -ystep * cs.y;
 #pragma unroll
                 for (int p = 0; p < P; ++p, ek += dek, h += dh) {
-                    // the pixel's window: m_lo = ceil((s_k - H) / tau + c0)
-                    // with s_k = D (e.k) / h, shifted (never past a non-zero
-                    // cell) so that it stays inside the staged cells
+                    // the pixel's window: m_lo = ceil((c_k - H) / step + c0)
+                    // with c_k the pixel's coordinate (flat: its shadow
+                    // s_k = D (e.k) / h; parallel: e.k; arc: its angle
+                    // atan(e.k / h)), shifted (never past a non-zero cell) so
+                    // that it stays inside the staged cells
                     const float hf = (float)h, ekf = (float)ek;
-                    const float sk = (float)D * ekf * fast_rcp(hf);
-                    const int m_lo = (int)ceilf(fmaf(sk - H, itau, c0f));
+                    float ck;
+                    if constexpr (BEAM == FP_PARALLEL)
+                        ck = ekf;
+                    else if constexpr (BEAM == FP_FAN_ARC)
+                        ck = atanf(ekf * fast_rcp(hf));
+                    else
+                        ck = (float)D * ekf * fast_rcp(hf);
+                    const int m_lo = (int)ceilf(fmaf(ck - H, istep, c0f));
                     const int w0 = min(max(m_lo - M0 + kBackPad, 0),
                                        cnt + 2 * kBackPad - min(T, cnt + 2 * kBackPad));
                     const int m_first = M0 - kBackPad + w0;
-                    // s' = (D (e.k) - s_m h) / R_m and R_m L = D h + s_m (e.k) at
-                    // the window's first cell in FP64, then steps of one cell
-                    const double s_first = (m_first - c0) * tau;
-                    const Real num0 = (Real)(D * ek - s_first * h);
-                    const Real hr = (Real)h, ekr = (Real)ek;
-                    const Real ln0 = fma((Real)s_first, ekr, Dr * hr);
-                    const Real dnum = taur * hr, dln = taur * ekr;
+                    const int Tw = T <= kBackMaxUnrolled ? T : min(T, cnt + 2 * kBackPad);
                     Real part[NB];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) part[b] = 0;
-                    if (T <= kBackMaxUnrolled)
-                        back_window<Real, NB, CAP, true>(l, w0, T, num0, dnum, ln0, dln, part);
-                    else
-                        back_window<Real, NB, CAP, false>(l, w0, min(T, cnt + 2 * kBackPad), num0,
-                                                          dnum, ln0, dln, part);
+                    if constexpr (BEAM == FP_FAN_ARC) {
+                        if (T <= kBackMaxUnrolled)
+                            back_window_arc<Real, NB, CAP, true>(l, G, w0, Tw, m_first, ek, h, part);
+                        else
+                            back_window_arc<Real, NB, CAP, false>(l, G, w0, Tw, m_first, ek, h, part);
+                    } else {
+                        // s' = num / R_m and R_m L = ln with num = D (e.k) - s_m h,
+                        // ln = D h + s_m (e.k) (parallel: num = e.k - s_m,
+                        // ln = 1), at the window's first cell in FP64, then
+                        // steps of one cell
+                        const double s_first = (m_first - c0) * step;
+                        Real num0, dnum, ln0, dln;
+                        if constexpr (BEAM == FP_PARALLEL) {
+                            num0 = (Real)(ek - s_first);
+                            dnum = stepr;
+                            ln0 = Real(1);
+                            dln = Real(0);
+                        } else {
+                            num0 = (Real)(D * ek - s_first * h);
+                            const Real hr = (Real)h, ekr = (Real)ek;
+                            ln0 = fma((Real)s_first, ekr, Dr * hr);
+                            dnum = stepr * hr;
+                            dln = stepr * ekr;
+                        }
+                        if (T <= kBackMaxUnrolled)
+                            back_window<Real, NB, CAP, true>(l, w0, Tw, num0, dnum, ln0, dln, part);
+                        else
+                            back_window<Real, NB, CAP, false>(l, w0, Tw, num0, dnum, ln0, dln, part);
+                    }
 #pragma unroll
                     for (int b = 0; b < NB; ++b) blk[p][b] += part[b];
                 }
@@ -647,14 +743,15 @@ __device__ __forceinline__ void back_block(const DevGeom &G, int tx, int ty, int
     }
 }
 
-template <typename Real, int NB, int CAP, BackMode MODE>
+template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
 __global__ __launch_bounds__(kBackThreads) void back_kernel(DevGeom G, const Real *__restrict__ sino,
                                                             Real *__restrict__ img,
                                                             Real *__restrict__ partial,
                                                             const Real *__restrict__ col_w,
                                                             Real relaxation) {
-    back_block<Real, NB, CAP, MODE>(G, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z, sino, img,
-                                    partial, col_w, relaxation);
+    __shared__ BackLds<Real, NB, CAP> lds[2];
+    back_block<Real, NB, CAP, MODE, BEAM>(lds, G, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z,
+                                          sino, img, partial, col_w, relaxation);
 }
 
 // Sum of the view-group partials in group order, then the back kernel's
@@ -682,226 +779,5 @@ __global__ __launch_bounds__(256) void back_finalize_kernel(const Real *__restri
     }
 }
 
-// ---------------------------------------------------------------------------
-// Grouped SIRT step over several jobs: work-group b of a phase belongs to the
-// last job whose first work-group is <= b (jobs are in order).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int multi_job_of(const MultiArgs &A, unsigned b, bool back) {
-    int j = 0;
-    for (int k = 1; k < A.n; ++k)
-        if ((back ? A.job[k].back_begin : A.job[k].fwd_begin) <= b) j = k;
-    return j;
-}
-
-// Padded copies of every job's iterate: blockIdx.y = job; the blocks of a
-// job stride over its row copy and over the 32 x 32 tiles of its column copy.
-__global__ __launch_bounds__(256) void pad_multi_kernel(const MultiArgs A) {
-    __shared__ float tile[32][33];
-    const MultiJob &J = A.job[blockIdx.y];
-    const int nx = J.g.nx, ny = J.g.ny, nrows = max(nx, ny);
-    const int tid = threadIdx.y * 32 + threadIdx.x;
-    pad_rows_body<float>(J.image, J.rows, nx, ny, nrows, 1, (size_t)blockIdx.x * 256 + tid,
-                         (size_t)gridDim.x * 256);
-    const int ti = (nrows + 31) / 32, tp = (ny + 2 * kFwdPad + 31) / 32;
-    for (int t = blockIdx.x; t < ti * tp; t += gridDim.x)
-        pad_cols_tile<float>(J.image, J.cols, nx, ny, nrows, (t % ti) * 32, (t / ti) * 32, tile);
-}
-
-__global__ __launch_bounds__(kFwdThreads) void forward_multi_kernel(const MultiArgs A) {
-    const int j = multi_job_of(A, blockIdx.x, false);
-    const MultiJob &J = A.job[j];
-    const unsigned local = blockIdx.x - J.fwd_begin;
-    const unsigned bx = (J.g.nd + kFwdThreads - 1) / kFwdThreads;
-    forward_block<float, 1, FwdMode::kSirtResidual>(J.g, local / bx, local % bx, J.rows, J.cols,
-                                                   J.work, nullptr, J.y_meas, J.row_w);
-}
-
-template <int CAP>
-__global__ __launch_bounds__(kBackThreads) void back_multi_kernel(const MultiArgs A) {
-    const int j = multi_job_of(A, blockIdx.x, true);
-    const MultiJob &J = A.job[j];
-    const unsigned local = blockIdx.x - J.back_begin;
-    back_block<float, 1, CAP, BackMode::kSirtUpdate>(J.g, local % J.g.tiles_x, local / J.g.tiles_x,
-                                                    0, 1, J.work, J.image_out, nullptr, J.col_w,
-                                                    J.relaxation);
-}
-
-// ------------------------------- launchers ---------------------------------
-
-template <typename Real, int NB, FwdMode MODE>
-hipError_t launch_fwd_t(const DevGeom &g, const Real *img, Real *work, Real *out, int *counts,
-                        const Real *y_meas, const Real *row_w, hipStream_t stream) {
-    const Real *rows = nullptr, *cols = nullptr;
-    if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
-        const int nrows = std::max(g.nx, g.ny);
-        Real *wr = work;
-        Real *wc = work + (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
-        const size_t total = (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
-        const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
-        hipLaunchKernelGGL(pad_rows_kernel<Real>, dim3(blocks), dim3(256), 0, stream, img, wr, g.nx,
-                           g.ny, nrows, NB);
-        dim3 tgrid((nrows + 31) / 32, (g.ny + 2 * kFwdPad + 31) / 32, NB);
-        hipLaunchKernelGGL(pad_cols_kernel<Real>, tgrid, dim3(32, 8), 0, stream, img, wc, g.nx,
-                           g.ny, nrows);
-        rows = wr;
-        cols = wc;
-    }
-    dim3 grid((g.nd + kFwdThreads - 1) / kFwdThreads, g.nv);
-    hipLaunchKernelGGL((forward_kernel<Real, NB, MODE>), grid, dim3(kFwdThreads), 0, stream, g,
-                       rows, cols, out, counts, y_meas, row_w);
-    return hipGetLastError();
-}
-
-template <typename Real, FwdMode MODE>
-hipError_t launch_fwd_nb(const DevGeom &g, int nb, const Real *img, Real *work, Real *out,
-                         int *counts, const Real *y_meas, const Real *row_w, hipStream_t stream) {
-    switch (nb) {
-        case 1: return launch_fwd_t<Real, 1, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
-        case 2: return launch_fwd_t<Real, 2, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
-        case 4: return launch_fwd_t<Real, 4, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
-        case 8: return launch_fwd_t<Real, 8, MODE>(g, img, work, out, counts, y_meas, row_w, stream);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename Real, int NB, int CAP>
-constexpr bool back_fits() {
-    return 2 * (size_t)(kBackRayParams + NB) * CAP * sizeof(Real) <= kBackLdsLimit;
-}
-
-template <typename Real, int NB, int CAP, BackMode MODE>
-hipError_t launch_back_t(const DevGeom &g, const Real *sino, Real *img, Real *partial,
-                         const Real *col_w, Real relaxation, hipStream_t stream) {
-    if constexpr (!back_fits<Real, NB, CAP>()) {
-        return hipErrorInvalidValue;  // excluded by back_max_batch
-    } else {
-        const int groups = partial ? g.back_groups : 1;
-        dim3 grid(g.tiles_x, g.tiles_y, groups);
-        hipLaunchKernelGGL((back_kernel<Real, NB, CAP, MODE>), grid, dim3(kBackThreads), 0, stream,
-                           g, sino, img, partial, col_w, relaxation);
-        if (groups > 1) {
-            const size_t npix = (size_t)g.nx * g.ny;
-            const unsigned blocks = (unsigned)std::min<size_t>((npix + 255) / 256, 4096);
-            hipLaunchKernelGGL((back_finalize_kernel<Real, NB, MODE>), dim3(blocks), dim3(256), 0,
-                               stream, partial, groups, npix, img, col_w, relaxation);
-        }
-        return hipGetLastError();
-    }
-}
-
-template <typename Real, int NB, BackMode MODE>
-hipError_t launch_back_cap(const DevGeom &g, const Real *sino, Real *img, Real *partial,
-                           const Real *col_w, Real relaxation, hipStream_t stream) {
-    switch (g.back_cap) {
-        case 64: return launch_back_t<Real, NB, 64, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        case 128: return launch_back_t<Real, NB, 128, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        case 256: return launch_back_t<Real, NB, 256, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        case 512: return launch_back_t<Real, NB, 512, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        case 1024: return launch_back_t<Real, NB, 1024, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename Real, BackMode MODE>
-hipError_t launch_back_nb(const DevGeom &g, int nb, const Real *sino, Real *img, Real *partial,
-                          const Real *col_w, Real relaxation, hipStream_t stream) {
-    switch (nb) {
-        case 1: return launch_back_cap<Real, 1, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        case 2: return launch_back_cap<Real, 2, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        case 4: return launch_back_cap<Real, 4, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        case 8: return launch_back_cap<Real, 8, MODE>(g, sino, img, partial, col_w, relaxation, stream);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 }  // namespace
-
-template <typename Real>
-size_t forward_work_bytes(const DevGeom &g, int nb) {
-    const size_t nrows = (size_t)std::max(g.nx, g.ny);
-    return (size_t)nb * sizeof(Real) * nrows * ((size_t)(g.nx + 2 * kFwdPad) + (g.ny + 2 * kFwdPad));
-}
-
-template <typename Real>
-int back_max_batch(const DevGeom &g) {
-    if (g.back_cap <= 0) return 0;
-    // two LDS buffers of (kBackRayParams + nb) arrays of back_cap values
-    for (int nb = kMaxBatchChunk; nb >= 1; nb /= 2)
-        if (2 * (size_t)(kBackRayParams + nb) * g.back_cap * sizeof(Real) <= kBackLdsLimit) return nb;
-    return 0;
-}
-
-template <typename Real>
-size_t back_work_bytes(const DevGeom &g, int nb) {
-    return g.back_groups > 1 ? (size_t)g.back_groups * nb * g.nx * g.ny * sizeof(Real) : 0;
-}
-
-template <typename Real>
-hipError_t launch_forward(const DevGeom &g, FwdMode mode, int nb, const Real *img, Real *work,
-                          Real *out, int *counts, const Real *y_meas, const Real *row_w,
-                          hipStream_t stream) {
-    switch (mode) {
-        case FwdMode::kPlain:
-            return launch_fwd_nb<Real, FwdMode::kPlain>(g, nb, img, work, out, counts, y_meas,
-                                                        row_w, stream);
-        case FwdMode::kSirtResidual:
-            return launch_fwd_nb<Real, FwdMode::kSirtResidual>(g, nb, img, work, out, counts,
-                                                               y_meas, row_w, stream);
-        case FwdMode::kOnes:
-            return launch_fwd_t<Real, 1, FwdMode::kOnes>(g, img, work, out, counts, y_meas, row_w,
-                                                         stream);
-        case FwdMode::kCount:
-            return launch_fwd_t<Real, 1, FwdMode::kCount>(g, img, work, out, counts, y_meas, row_w,
-                                                          stream);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename Real>
-hipError_t launch_back(const DevGeom &g, BackMode mode, int nb, const Real *sino, Real *img,
-                       Real *partial, const Real *col_w, Real relaxation, hipStream_t stream) {
-    switch (mode) {
-        case BackMode::kPlain:
-            return launch_back_nb<Real, BackMode::kPlain>(g, nb, sino, img, partial, col_w,
-                                                          relaxation, stream);
-        case BackMode::kSirtUpdate:
-            return launch_back_nb<Real, BackMode::kSirtUpdate>(g, nb, sino, img, partial, col_w,
-                                                               relaxation, stream);
-        case BackMode::kOnes:
-            return launch_back_cap<Real, 1, BackMode::kOnes>(g, sino, img, partial, col_w,
-                                                             relaxation, stream);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_sirt_multi(const MultiArgs &A, hipStream_t stream) {
-    if (A.n < 1) return hipSuccess;
-    int cap = 0;
-    for (int k = 0; k < A.n; ++k) cap = std::max(cap, A.job[k].g.back_cap);
-    hipLaunchKernelGGL(pad_multi_kernel, dim3(64, A.n), dim3(32, 8), 0, stream, A);
-    hipLaunchKernelGGL(forward_multi_kernel, dim3(A.fwd_blocks), dim3(kFwdThreads), 0, stream, A);
-    switch (cap) {
-        case 64: hipLaunchKernelGGL(back_multi_kernel<64>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 128: hipLaunchKernelGGL(back_multi_kernel<128>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 256: hipLaunchKernelGGL(back_multi_kernel<256>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 512: hipLaunchKernelGGL(back_multi_kernel<512>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 1024: hipLaunchKernelGGL(back_multi_kernel<1024>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-#define FANPROJ_INSTANTIATE(Real)                                                                  \
-    template size_t forward_work_bytes<Real>(const DevGeom &, int);                                \
-    template int back_max_batch<Real>(const DevGeom &);                                            \
-    template size_t back_work_bytes<Real>(const DevGeom &, int);                                   \
-    template hipError_t launch_forward<Real>(const DevGeom &, FwdMode, int, const Real *, Real *,  \
-                                             Real *, int *, const Real *, const Real *,            \
-                                             hipStream_t);                                          \
-    template hipError_t launch_back<Real>(const DevGeom &, BackMode, int, const Real *, Real *,    \
-                                          Real *, const Real *, Real, hipStream_t);
-FANPROJ_INSTANTIATE(float)
-FANPROJ_INSTANTIATE(double)
-#undef FANPROJ_INSTANTIATE
-
 }  // namespace fanproj

@@ -22,6 +22,11 @@ FP_ERR_OUT_OF_MEMORY = 2
 FP_ERR_DEVICE = 3
 FP_ERR_UNSUPPORTED = 4
 
+FP_FAN_FLAT = 0
+FP_FAN_ARC = 1
+FP_PARALLEL = 2
+BEAMS = {"flat": FP_FAN_FLAT, "arc": FP_FAN_ARC, "parallel": FP_PARALLEL}
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
                       "`python -c 'import __graft_entry__ as g; g.build()'` "
@@ -33,6 +38,17 @@ _lib.fp_geometry_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_dou
                                     ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                     ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_vp)]
 _lib.fp_geometry_create.restype = ctypes.c_int
+class FpGeometryDesc(ctypes.Structure):
+    """fp_geometry_desc of the C ABI."""
+    _fields_ = [("beam", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("pixel_size", ctypes.c_double), ("dist_source_center", ctypes.c_double),
+                ("dist_source_detector", ctypes.c_double), ("n_views", ctypes.c_int32),
+                ("view_angles", ctypes.POINTER(ctypes.c_double)), ("n_det", ctypes.c_int32),
+                ("det_pitch", ctypes.c_double), ("det_width", ctypes.c_double)]
+
+
+_lib.fp_geometry_create_desc.argtypes = [ctypes.POINTER(FpGeometryDesc), ctypes.POINTER(_vp)]
+_lib.fp_geometry_create_desc.restype = ctypes.c_int
 _lib.fp_geometry_destroy.argtypes = [_vp]
 _lib.fp_geometry_destroy.restype = ctypes.c_int
 _lib.fp_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
@@ -63,7 +79,7 @@ _lib.fp_geometry_device_bytes.restype = ctypes.c_size_t
 _lib.fp_last_error.argtypes = []
 _lib.fp_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ("fp_geometry_create", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_forward_f64",
+EXPORTED = ("fp_geometry_create", "fp_geometry_create_desc", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_forward_f64",
             "fp_back_f64", "fp_sirt_step", "fp_sirt_prepare", "fp_sirt_step_multi",
             "fp_count_nonzero", "fp_geometry_device_bytes", "fp_last_error")
 
@@ -112,6 +128,18 @@ def fp_geometry_create(nx, ny, pixel_size, dist_source_center, dist_source_detec
                                    float(dist_source_detector), int(ang.size),
                                    ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                    int(n_det), float(det_width), ctypes.byref(h)))
+    return h
+
+
+def fp_geometry_create_desc(beam, nx, ny, pixel_size, dist_source_center, dist_source_detector,
+                            view_angles, n_det, det_pitch, det_width) -> ctypes.c_void_p:
+    ang = np.ascontiguousarray(np.asarray(view_angles, dtype=np.float64))
+    d = FpGeometryDesc(int(beam), int(nx), int(ny), float(pixel_size), float(dist_source_center),
+                       float(dist_source_detector), int(ang.size),
+                       ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_det),
+                       float(det_pitch), float(det_width))
+    h = ctypes.c_void_p()
+    _check(_lib.fp_geometry_create_desc(ctypes.byref(d), ctypes.byref(h)))
     return h
 
 
@@ -180,15 +208,23 @@ class Geometry:
 
     Images are ``[batch, ny, nx]`` (or ``[ny, nx]``), sinograms
     ``[batch, n_views, n_det]`` (or ``[n_views, n_det]``), float32 on the
-    geometry's GPU.
+    geometry's GPU.  ``beam`` is "flat" (fan beam, flat detector), "arc" (fan
+    beam, arc detector) or "parallel"; ``det_pitch`` defaults to the width.
     """
 
-    def __init__(self, nx, ny, pixel, dsc, dsd, angles, n_det, det_width):
+    def __init__(self, nx, ny, pixel, dsc, dsd, angles, n_det, det_width, beam="flat",
+                 det_pitch=None):
         self.nx, self.ny, self.n_det = int(nx), int(ny), int(n_det)
         self.angles = np.asarray(angles, dtype=np.float64)
         self.n_views = int(self.angles.size)
         self.pixel, self.dsc, self.dsd, self.det_width = float(pixel), float(dsc), float(dsd), float(det_width)
-        self.handle = fp_geometry_create(nx, ny, pixel, dsc, dsd, self.angles, n_det, det_width)
+        self.det_pitch = float(det_width if det_pitch is None else det_pitch)
+        self.beam = beam
+        if beam == "flat" and det_pitch is None:
+            self.handle = fp_geometry_create(nx, ny, pixel, dsc, dsd, self.angles, n_det, det_width)
+        else:
+            self.handle = fp_geometry_create_desc(BEAMS[beam], nx, ny, pixel, dsc, dsd, self.angles,
+                                                  n_det, self.det_pitch, det_width)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -84,3 +84,45 @@ def test_null_arguments_rejected(lib):
     lib.fp_count_nonzero.restype = ctypes.c_int
     assert lib.fp_count_nonzero(None, ctypes.byref(out), None) == 1
     assert b"NULL" in lib.fp_last_error()
+
+
+def _create_desc(lib, **kw):
+    from paper_1907_10526_amd import fanproj
+    args = dict(beam=0, nx=64, ny=64, pixel=1.0, dsc=128.0, dsd=256.0, n_views=4, n_det=128,
+                pitch=1.5, width=1.5)
+    args.update(kw)
+    ang = np.linspace(0, 1, max(args["n_views"], 1))
+    d = fanproj.FpGeometryDesc(args["beam"], args["nx"], args["ny"], args["pixel"], args["dsc"],
+                               args["dsd"], args["n_views"],
+                               ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), args["n_det"],
+                               args["pitch"], args["width"])
+    out = ctypes.c_void_p()
+    f = lib.fp_geometry_create_desc
+    f.restype = ctypes.c_int
+    st = f(ctypes.byref(d), ctypes.byref(out))
+    lib.fp_last_error.restype = ctypes.c_char_p
+    return st, lib.fp_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(beam=7), "unknown beam"), (dict(pitch=0.0), "pitch"), (dict(pitch=float("inf")), "pitch"),
+    (dict(beam=1, n_det=2000, pitch=0.5), "80 degrees"), (dict(beam=1, dsd=100.0), "exceed"),
+    (dict(beam=2, nx=0), ">= 1"), (dict(beam=2, width=-1.0), "finite"),
+])
+def test_invalid_description_rejected_without_device(lib, kw, needle):
+    st, msg = _create_desc(lib, **kw)
+    assert st == 1, (st, msg)
+    assert needle in msg
+
+
+def test_parallel_description_ignores_distances(lib):
+    # distances a fan geometry would reject pass validation for parallel
+    # beams; on a host without a device the call then fails at the device
+    st, msg = _create_desc(lib, beam=2, dsc=0.0, dsd=float("nan"))
+    assert st != 1, msg
+
+
+def test_null_description_rejected(lib):
+    out = ctypes.c_void_p()
+    lib.fp_geometry_create_desc.restype = ctypes.c_int
+    assert lib.fp_geometry_create_desc(None, ctypes.byref(out)) == 1
