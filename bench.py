@@ -81,6 +81,20 @@ def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample, min_se
            "sample": f"forward rows and back partial sums of views 0..{k - 1} of {scan.n_views}, "
                      f"{reps} times ({t_fwd:.1f} s + {t_back:.1f} s in all, FP64), "
                      f"scaled by {scan.n_views}/{k} per pass"}
+    # one core, on a smaller sample of the same workload
+    k1 = max(1, min(24, k))
+    n_all = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        og.forward_views(img64, 0, k1)
+        og.back_views(sino64, 0, k1)
+        t1 = time.perf_counter()
+    finally:
+        oracle.set_threads(n_all)
+    rec["single_core"] = {"value": (k1 / scan.n_views) / (t1 - t0), "unit": "pairs/s", "cores": 1,
+                          "sample": f"forward rows and back partial sums of views 0..{k1 - 1} "
+                                    f"({t1 - t0:.1f} s, FP64), scaled by {scan.n_views}/{k1}"}
     rel = {
         "forward": float(np.linalg.norm(y_gpu_rows - y_ref) / np.linalg.norm(y_ref)),
         "back": float(np.linalg.norm(z_gpu_part - z_ref) / np.linalg.norm(z_ref)),

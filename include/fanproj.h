@@ -175,6 +175,23 @@ fp_status fp_forward_f64(const fp_geometry *g, const double *image, double *sino
 fp_status fp_back_f64(const fp_geometry *g, const double *sino, double *image,
                       int32_t batch, void *stream);
 
+/* The reference projector of the paper's experiments (Sec. V): entry
+ * (v, m, k) is the exact length of the ray through pixel k, averaged over the
+ * cell's detector coordinate (arc length for the arc detector; eq. (2)-(3)
+ * with the unit-mass blur), with no effective-blur approximation.  Between
+ * the rays through the pixel's four corners the chord is smooth, so each
+ * piece is integrated by Gauss-Legendre quadrature with quad_points nodes
+ * (0 selects 16; at most 24), which reaches FP64 rounding for smooth pieces.
+ * FP64 in and out, layouts as fp_forward / fp_back, outputs overwritten;
+ * fp_back_reference is the exact adjoint of fp_forward_reference (same
+ * entries).  For parallel beams the reference equals the CNSF model
+ * (Theorem 1).  Slow by design (thousands of flops per entry): a yardstick
+ * for accuracy experiments, not a production path. */
+fp_status fp_forward_reference(const fp_geometry *g, const double *image, double *sino,
+                               int32_t batch, int32_t quad_points, void *stream);
+fp_status fp_back_reference(const fp_geometry *g, const double *sino, double *image,
+                            int32_t batch, int32_t quad_points, void *stream);
+
 /* One SIRT step (simultaneous iterative reconstruction; the iterative family
  * the paper targets, Sec. I):
  *     x <- x + relaxation * C .* A^T( R .* (y - A x) ),

@@ -274,6 +274,41 @@ extern "C" fp_status fp_back_f64(const fp_geometry *g, const double *sino, doubl
     return back_impl<double>(g, sino, image, batch, stream, "fp_back_f64");
 }
 
+namespace fanproj {
+namespace {
+
+fp_status reference_impl(const fp_geometry *g, bool forward, const double *in, double *out,
+                         int32_t batch, int32_t quad, void *stream, const char *fn) {
+    clear_error();
+    fp_status st = check_call(g, batch, fn);
+    if (st != FP_OK) return st;
+    if (quad < 0 || quad > 24) {
+        set_error(std::string(fn) + ": quad_points must be 0 (default 16) or 1 .. 24");
+        return FP_ERR_INVALID_ARG;
+    }
+    DeviceGuard guard(g->device);
+    if (guard.status() != hipSuccess) return device_error(fn, guard.status());
+    if ((st = check_device_ptr(in, g->device, forward ? "image" : "sino")) != FP_OK) return st;
+    if ((st = check_device_ptr(out, g->device, forward ? "sino" : "image")) != FP_OK) return st;
+    const hipError_t e = launch_reference(g, forward, in, out, batch, quad ? quad : 16,
+                                          static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(fn, e);
+    return FP_OK;
+}
+
+}  // namespace
+}  // namespace fanproj
+
+extern "C" fp_status fp_forward_reference(const fp_geometry *g, const double *image, double *sino,
+                                          int32_t batch, int32_t quad_points, void *stream) {
+    return reference_impl(g, true, image, sino, batch, quad_points, stream, "fp_forward_reference");
+}
+
+extern "C" fp_status fp_back_reference(const fp_geometry *g, const double *sino, double *image,
+                                       int32_t batch, int32_t quad_points, void *stream) {
+    return reference_impl(g, false, sino, image, batch, quad_points, stream, "fp_back_reference");
+}
+
 extern "C" fp_status fp_sirt_step(const fp_geometry *g_const, float *image, const float *sino_meas,
                                   float relaxation, float *work, int32_t batch, void *stream) {
     clear_error();

@@ -205,6 +205,10 @@ struct fp_geometry {
 };
 
 namespace fanproj {
+// The reference projector (reference.hip): forward (true) or its adjoint
+// over `batch` images, FP64, `quad` Gauss-Legendre points per smooth piece.
+hipError_t launch_reference(const fp_geometry *g, bool forward, const double *in, double *out,
+                            int batch, int quad, hipStream_t s);
 // Uploads the FP64 per-ray tables if they are not there yet (thread-safe).
 fp_status ensure_f64_tables(fp_geometry *g);
 // Thread-local error text used by fp_last_error.

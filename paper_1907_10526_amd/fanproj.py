@@ -59,6 +59,10 @@ _lib.fp_forward_f64.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
 _lib.fp_forward_f64.restype = ctypes.c_int
 _lib.fp_back_f64.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp]
 _lib.fp_back_f64.restype = ctypes.c_int
+_lib.fp_forward_reference.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]
+_lib.fp_forward_reference.restype = ctypes.c_int
+_lib.fp_back_reference.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]
+_lib.fp_back_reference.restype = ctypes.c_int
 _lib.fp_sirt_step.argtypes = [_vp, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32, _vp]
 _lib.fp_sirt_step.restype = ctypes.c_int
 class FpSirtJob(ctypes.Structure):
@@ -80,7 +84,7 @@ _lib.fp_last_error.argtypes = []
 _lib.fp_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ("fp_geometry_create", "fp_geometry_create_desc", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_forward_f64",
-            "fp_back_f64", "fp_sirt_step", "fp_sirt_prepare", "fp_sirt_step_multi",
+            "fp_back_f64", "fp_forward_reference", "fp_back_reference", "fp_sirt_step", "fp_sirt_prepare", "fp_sirt_step_multi",
             "fp_count_nonzero", "fp_geometry_device_bytes", "fp_last_error")
 
 
@@ -169,6 +173,20 @@ def fp_back_f64(handle, sino, image, batch, stream=None) -> None:
     _check(_lib.fp_back_f64(handle, _dev_ptr(sino, "sino", dtype=torch.float64),
                             _dev_ptr(image, "image", dtype=torch.float64), int(batch),
                             _stream_handle(stream)))
+
+
+def fp_forward_reference(handle, image, sino, batch, quad_points=0, stream=None) -> None:
+    import torch
+    _check(_lib.fp_forward_reference(handle, _dev_ptr(image, "image", dtype=torch.float64),
+                                     _dev_ptr(sino, "sino", dtype=torch.float64), int(batch),
+                                     int(quad_points), _stream_handle(stream)))
+
+
+def fp_back_reference(handle, sino, image, batch, quad_points=0, stream=None) -> None:
+    import torch
+    _check(_lib.fp_back_reference(handle, _dev_ptr(sino, "sino", dtype=torch.float64),
+                                  _dev_ptr(image, "image", dtype=torch.float64), int(batch),
+                                  int(quad_points), _stream_handle(stream)))
 
 
 def fp_sirt_step(handle, image, sino_meas, relaxation, work, batch, stream=None) -> None:
@@ -263,6 +281,26 @@ class Geometry:
             shape = (self.ny, self.nx) if sino.dim() == 2 else (b, self.ny, self.nx)
             out = torch.empty(shape, dtype=sino.dtype, device=sino.device)
         (fp_back_f64 if sino.dtype == torch.float64 else fp_back)(self.handle, sino, out, b, stream)
+        return out
+
+    def forward_reference(self, image, out=None, quad_points=0, stream=None):
+        """The exact reference projection (FP64) of an image or a batch."""
+        import torch
+        b = self._batch(image, (self.ny, self.nx), "image")
+        if out is None:
+            shape = (self.n_views, self.n_det) if image.dim() == 2 else (b, self.n_views, self.n_det)
+            out = torch.empty(shape, dtype=torch.float64, device=image.device)
+        fp_forward_reference(self.handle, image, out, b, quad_points, stream)
+        return out
+
+    def back_reference(self, sino, out=None, quad_points=0, stream=None):
+        """The adjoint of forward_reference (FP64)."""
+        import torch
+        b = self._batch(sino, (self.n_views, self.n_det), "sino")
+        if out is None:
+            shape = (self.ny, self.nx) if sino.dim() == 2 else (b, self.ny, self.nx)
+            out = torch.empty(shape, dtype=torch.float64, device=sino.device)
+        fp_back_reference(self.handle, sino, out, b, quad_points, stream)
         return out
 
     def sirt_step(self, image, sino_meas, relaxation=1.0, work=None, stream=None):
