@@ -29,6 +29,29 @@ FLOPS_PER_ENTRY = 48
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of each kernel at this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs of this script, each scaled by what the same
+# counter reads for a 256 MiB device copy in the same run (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0); the summary and commands are in profiles/.  Valid only
+# for the kernel sources they were taken on: `traffic` is reported as null
+# once the hash of those sources differs.
+TRAFFIC = {
+    "sources_sha256": "41ce183a0b0afcf42b4fb40a0704a706b37909d062bc1f489177e77f7628fea7",
+    "bytes_per_launch": {"forward": 36007911, "back": 232203166},
+    "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
+}
+TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",
+                   "back_flat_f32.hip"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1907_10526_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -187,8 +210,12 @@ def main():
     kernels = {"forward": float(fwd_ms.mean()), "back": float(bck_ms.mean())}
     dom = max(kernels, key=kernels.get)
     achieved = flops / (kernels[dom] * 1e-3) / 1e12
+    traffic = None
+    if TRAFFIC["sources_sha256"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+        traffic = TRAFFIC["bytes_per_launch"].get(dom)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch", "traffic_profile": TRAFFIC["profile"],
                 "flops_per_launch": flops, "entries_per_launch": nnz,
                 "flops_per_entry": FLOPS_PER_ENTRY,
                 "avg_ms": {k: round(v, 5) for k, v in kernels.items()},
