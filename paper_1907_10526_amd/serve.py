@@ -158,7 +158,7 @@ class Server:
     """
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
-                 step_work: float = 4e9, clock=None, keep_outputs: bool = False):
+                 step_work: float = 1.5e10, clock=None, keep_outputs: bool = False):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
