@@ -154,26 +154,59 @@ class Server:
 
     hbm_budget: bytes the admitted jobs may hold together (a job larger than
     the budget is admitted alone when nothing else runs); max_active: slot
-    limit.
+    limit; step_work: matrix entries one step may evaluate (the oldest job
+    always goes).
+
+    With an executor that can launch a step without waiting for it
+    (``launch`` returning a token and ``wait`` on a token), the loop keeps
+    ``depth`` steps in flight: it launches step k + 1 before waiting for step
+    k, so the device never idles while the host schedules, and a job's
+    completion time is when the wait on its last step returns.  Releasing a
+    job's geometry synchronises the device, so finished jobs are released
+    when their memory is needed for admission or when nothing is in flight.
     """
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
-                 step_work: float = 1.5e10, clock=None, keep_outputs: bool = False):
+                 step_work: float = 1.5e10, clock=None, keep_outputs: bool = False,
+                 depth: int = 2):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.step_work = float(step_work)
         self.clock = clock or RealClock()
         self.keep_outputs = keep_outputs
+        self.depth = max(1, int(depth))
 
     def run(self, trace) -> ServeResult:
         res = ServeResult()
         pending = deque(sorted(trace, key=lambda s: (s.arrival, s.job_id)))
         waiting = deque()
-        active: list = []
+        active: list = []          # admitted jobs with iterations left to launch
+        inflight = deque()         # (token, jobs whose last iteration it holds)
+        done = []                  # finished jobs not yet released
         used = 0
         clock = self.clock
-        while pending or waiting or active:
+        pipelined = hasattr(self.ex, "launch") and hasattr(self.ex, "wait")
+
+        def release_done():
+            nonlocal used
+            for a in done:
+                if self.keep_outputs:
+                    res.outputs[a.spec.job_id] = self.ex.result(a.handle)
+                self.ex.release(a.handle)
+                used -= a.nbytes
+            done.clear()
+
+        def retire(token, finishing):
+            if pipelined:
+                self.ex.wait(token)
+            t = clock.now()
+            for a in finishing:
+                res.finished[a.spec.job_id] = t
+                res.latency[a.spec.job_id] = t - a.spec.arrival
+                done.append(a)
+
+        while pending or waiting or active or inflight or done:
             now = clock.now()
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
@@ -181,7 +214,12 @@ class Server:
             while waiting and len(active) < self.max_active:
                 spec = waiting[0]
                 need = job_device_bytes(spec)
-                if active and used + need > self.budget:
+                if (active or inflight or done) and used + need > self.budget:
+                    if done:                      # free finished jobs first
+                        while inflight:
+                            retire(*inflight.popleft())
+                        release_done()
+                        continue
                     break
                 waiting.popleft()
                 handle = self.ex.prepare(spec)
@@ -191,42 +229,40 @@ class Server:
                 res.order.append(spec.job_id)
             res.peak_active = max(res.peak_active, len(active))
             res.peak_bytes = max(res.peak_bytes, used)
-            if not active:
-                if pending:
-                    clock.wait_until(pending[0].arrival)
+            if active:
+                # one SIRT iteration for the oldest admitted jobs that fit the
+                # step's work budget (first fit in admission order: the oldest
+                # job always goes, a job that does not fit leaves room for
+                # younger, smaller ones), in grouped launches
+                batch, work = [], 0.0
+                for a in active:
+                    w = job_iteration_work(a.spec)
+                    if batch and work + w > self.step_work:
+                        continue
+                    batch.append(a)
+                    work += w
+                handles = [a.handle for a in batch]
+                token = self.ex.launch(handles) if pipelined else self.ex.step(handles)
+                res.steps += 1
+                res.batch_sizes.append(len(batch))
+                finishing = []
+                for a in batch:
+                    a.done_iters += 1
+                    if a.done_iters >= a.spec.iters:
+                        finishing.append(a)
+                if finishing:
+                    fin = {id(a) for a in finishing}
+                    active = [a for a in active if id(a) not in fin]
+                inflight.append((token, finishing))
+                while len(inflight) > (self.depth - 1 if pipelined else 0):
+                    retire(*inflight.popleft())
                 continue
-            # one SIRT iteration for the oldest admitted jobs that fit the
-            # step's work budget, in grouped launches
-            # (first fit in admission order: the oldest job always goes, a
-            # job that does not fit leaves room for younger, smaller ones)
-            batch, work = [], 0.0
-            for a in active:     # admission order = arrival order
-                w = job_iteration_work(a.spec)
-                if batch and work + w > self.step_work:
-                    continue
-                batch.append(a)
-                work += w
-            self.ex.step([a.handle for a in batch])
-            res.steps += 1
-            res.batch_sizes.append(len(batch))
-            t_done = clock.now()
-            stepped = {id(a) for a in batch}
-            still = []
-            for a in active:
-                if id(a) not in stepped:
-                    still.append(a)
-                    continue
-                a.done_iters += 1
-                if a.done_iters >= a.spec.iters:
-                    res.finished[a.spec.job_id] = t_done
-                    res.latency[a.spec.job_id] = t_done - a.spec.arrival
-                    if self.keep_outputs:
-                        res.outputs[a.spec.job_id] = self.ex.result(a.handle)
-                    self.ex.release(a.handle)
-                    used -= a.nbytes
-                else:
-                    still.append(a)
-            active = still
+            # nothing left to launch: drain, free, then wait for arrivals
+            while inflight:
+                retire(*inflight.popleft())
+            release_done()
+            if pending and not waiting:
+                clock.wait_until(pending[0].arrival)
         res.makespan = clock.now()
         return res
 
@@ -291,6 +327,16 @@ class GpuExecutor:
     def step(self, handles) -> None:
         self.fp.fp_sirt_step_multi([(g.handle, x, y, w, 1.0) for g, x, y, w in handles])
         self.torch.cuda.synchronize(self.device)
+
+    def launch(self, handles):
+        """Queue one grouped SIRT step; returns an event recorded after it."""
+        self.fp.fp_sirt_step_multi([(g.handle, x, y, w, 1.0) for g, x, y, w in handles])
+        ev = self.torch.cuda.Event()
+        ev.record()
+        return ev
+
+    def wait(self, token) -> None:
+        token.synchronize()
 
     def run_job(self, h, iters: int) -> None:
         g, x, y, w = h

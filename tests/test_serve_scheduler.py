@@ -138,16 +138,18 @@ def test_step_work_budget_keeps_fifo_priority():
     res = serve.Server(ex, hbm_budget=1 << 40, step_work=big, clock=clock).run(trace)
     assert len(res.latency) == 30
     order = {j: k for k, j in enumerate(res.order)}
-    live = set()
+    iterating, steps = set(), {}
     for kind, handles, _ in ex.log:
         if kind == "prepare":
-            live.add(handles)
-        elif kind == "release":
-            live.discard(handles)
-        else:
+            iterating.add(handles)
+        elif kind == "step":
             ks = [order[h] for h in handles]
             assert ks == sorted(ks)                           # admission order
-            assert ks[0] == min(order[h] for h in live)       # the oldest live job
+            assert ks[0] == min(order[h] for h in iterating)  # the oldest unfinished job
+            for h in handles:
+                steps[h] = steps.get(h, 0) + 1
+                if steps[h] == trace[h].iters:
+                    iterating.discard(h)
             tot = sum(serve.job_iteration_work(trace[h]) for h in handles)
             assert len(handles) == 1 or tot <= big
 
@@ -182,3 +184,81 @@ def test_work_budget_improves_median_over_unbounded_batching():
     a, b = serve.latency_stats(runs["unbounded"]), serve.latency_stats(runs["bounded"])
     assert b["p50_s"] < a["p50_s"]
     assert b["makespan_s"] <= a["makespan_s"] * 1.05
+
+
+class AsyncFakeExecutor(FakeExecutor):
+    """launch() queues a step on a simulated device timeline and costs the
+    host only `host` seconds; wait() advances the clock to the step's end;
+    release() synchronises with the device (as destroying a geometry does)."""
+
+    def __init__(self, clock, host=1e-3, **kw):
+        super().__init__(clock, **kw)
+        self.host = host
+        self.busy_until = 0.0
+
+    def launch(self, handles):
+        tot = sum(self.work(self.live[h]) for h in handles)
+        big = max(self.work(self.live[h]) for h in handles)
+        self.clock.advance(self.host)
+        start = max(self.busy_until, self.clock.now())
+        self.busy_until = start + max(tot / self.width, big)
+        self.log.append(("step", tuple(handles), self.busy_until))
+        return self.busy_until
+
+    def wait(self, token):
+        self.clock.wait_until(token)
+
+    def release(self, h):
+        self.clock.wait_until(self.busy_until)
+        super().release(h)
+
+
+class SyncFakeExecutor(FakeExecutor):
+    """The same costs without overlap: host launch cost plus device time."""
+
+    def __init__(self, clock, host=1e-3, **kw):
+        super().__init__(clock, overhead=host, **kw)
+
+
+def test_pipelined_loop_is_complete_and_within_budget():
+    clock = serve.SimClock()
+    ex = AsyncFakeExecutor(clock)
+    trace = _trace(count=40, rate=80.0, iters=6)
+    budget = 4 * max(serve.job_device_bytes(s) for s in trace)
+    res = serve.Server(ex, hbm_budget=budget, clock=clock).run(trace)
+    assert sorted(res.latency) == [s.job_id for s in trace]
+    assert not ex.live
+    steps = {}
+    live, used = set(), 0
+    sizes = {s.job_id: serve.job_device_bytes(s) for s in trace}
+    for kind, x, t in ex.log:
+        if kind == "prepare":
+            live.add(x)
+            used += sizes[x]
+            assert used <= budget
+        elif kind == "release":
+            live.discard(x)
+            used -= sizes[x]
+        else:
+            for h in x:
+                assert h in live
+                steps[h] = steps.get(h, 0) + 1
+    assert all(steps[s.job_id] == s.iters for s in trace)
+    for s in trace:        # a job completes no earlier than its last step ends
+        last = max(t for kind, x, t in ex.log if kind == "step" and s.job_id in x)
+        assert res.finished[s.job_id] >= last - 1e-12
+
+
+def test_pipelining_overlaps_host_and_device():
+    """Steps of a few milliseconds with a host cost of 1 ms per launch: the
+    pipelined loop hides the host cost behind the device."""
+    trace = _trace(count=60, rate=200.0, iters=8)
+    kw = dict(host=1e-3, unit=2e-12)
+    c1 = serve.SimClock()
+    pipe = serve.Server(AsyncFakeExecutor(c1, **kw), hbm_budget=1 << 40, step_work=2e9,
+                        clock=c1).run(trace)
+    c2 = serve.SimClock()
+    sync = serve.Server(SyncFakeExecutor(c2, **kw), hbm_budget=1 << 40, step_work=2e9,
+                        clock=c2).run(trace)
+    assert pipe.makespan < sync.makespan
+    assert serve.latency_stats(pipe)["mean_s"] < serve.latency_stats(sync)["mean_s"]
