@@ -63,7 +63,7 @@ def parse():
                    help="views of the workload the FP64 oracle is timed on")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="repeat the oracle sample until this much time has passed (at most 8 passes)")
-    p.add_argument("--serve-jobs", type=int, default=200,
+    p.add_argument("--serve-jobs", type=int, default=1000,
                    help="jobs in the served-vs-plain comparison (0 skips it)")
     p.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
     p.add_argument("--serve-budget-gib", type=float, default=2.0,
@@ -74,6 +74,17 @@ def parse():
                    help="run one device-to-device copy of this many MiB before timing, as a "
                         "known-size reference for hardware byte counters")
     return p.parse_args()
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample, min_seconds):
@@ -101,6 +112,7 @@ def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample, min_se
     frac = k / scan.n_views
     secs = (t_fwd + t_back) / reps / frac  # seconds per full pair
     rec = {"value": 1.0 / secs, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
+           "seconds_per_pair": secs, "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
            "sample": f"forward rows and back partial sums of views 0..{k - 1} of {scan.n_views}, "
                      f"{reps} times ({t_fwd:.1f} s + {t_back:.1f} s in all, FP64), "
                      f"scaled by {scan.n_views}/{k} per pass"}
@@ -116,6 +128,7 @@ def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample, min_se
     finally:
         oracle.set_threads(n_all)
     rec["single_core"] = {"value": (k1 / scan.n_views) / (t1 - t0), "unit": "pairs/s", "cores": 1,
+                          "seconds_per_pair": (t1 - t0) * scan.n_views / k1,
                           "sample": f"forward rows and back partial sums of views 0..{k1 - 1} "
                                     f"({t1 - t0:.1f} s, FP64), scaled by {scan.n_views}/{k1}"}
     rel = {
@@ -134,16 +147,20 @@ def serving(args):
     trace = serve.make_trace(args.serve_jobs, args.serve_rate, seed=5)
     ex = serve.GpuExecutor()
     budget = int(args.serve_budget_gib * (1 << 30))
+    t0 = time.perf_counter()
     batched = serve.Server(ex, hbm_budget=budget, step_work=args.serve_step_work).run(trace)
-    unpiped = serve.Server(ex, hbm_budget=budget, step_work=args.serve_step_work, depth=1).run(trace)
+    print(f"serving: batched loop done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
     plain = serve.run_plain(ex, trace)
+    print(f"serving: plain path done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
     return {"trace": f"{args.serve_jobs} jobs, Poisson arrivals {args.serve_rate:g}/s (seed 5), "
                      "image side {256,512,1024}, views {180,360,720,1440}, cells 2 x side, "
                      "source-centre U[2,4] x side, magnification 1.5, 20 SIRT iterations",
             "hbm_budget_bytes": budget,
             "step_work_entries": args.serve_step_work,
             "batched": serve.latency_stats(batched),
-            "batched_one_step_in_flight": serve.latency_stats(unpiped),
             "plain": serve.latency_stats(plain)}
 
 
@@ -223,7 +240,8 @@ def main():
                                       for k, v in kernels.items()}}
 
     out = {
-        "metric": "projection pairs (A+A^T)/sec at 512^2x720 views",
+        "metric": "projection pairs (A+A\u1d40)/sec at 512\u00b2\u00d7720 views; p99 job latency; "
+                  "rel-L2 vs FP64",
         "value": K / (total_ms * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
