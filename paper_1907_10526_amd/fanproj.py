@@ -256,19 +256,29 @@ class Geometry:
             pass
 
     def _batch(self, t, shape, name):
-        if t.dim() == len(shape):
-            return 1
-        if t.dim() != len(shape) + 1:
-            raise ValueError(f"{name} must have shape {shape} or (batch, *{shape})")
-        return t.shape[0]
+        """Batch size of a [batch, *shape] or [*shape] tensor; anything else is
+        rejected before it reaches the kernels."""
+        if t.dim() not in (len(shape), len(shape) + 1) or tuple(t.shape[-len(shape):]) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)} or "
+                             f"(batch, *{tuple(shape)})")
+        return 1 if t.dim() == len(shape) else t.shape[0]
+
+    def _output(self, out, like, b, shape, dtype, name):
+        """The caller's output tensor, checked to hold exactly `b` results of
+        `shape`, or a new one."""
+        import torch
+        full = shape if like.dim() == len(shape) else (b, *shape)
+        if out is None:
+            return torch.empty(full, dtype=dtype, device=like.device)
+        if tuple(out.shape) != tuple(full) and not (b == 1 and tuple(out.shape) == tuple(shape)):
+            raise ValueError(f"{name} has shape {tuple(out.shape)}, expected {tuple(full)}")
+        return out
 
     def forward(self, image, out=None, stream=None):
         """A c for float32 (production kernels) or float64 (FP64 kernels)."""
         import torch
         b = self._batch(image, (self.ny, self.nx), "image")
-        if out is None:
-            shape = (self.n_views, self.n_det) if image.dim() == 2 else (b, self.n_views, self.n_det)
-            out = torch.empty(shape, dtype=image.dtype, device=image.device)
+        out = self._output(out, image, b, (self.n_views, self.n_det), image.dtype, "out")
         (fp_forward_f64 if image.dtype == torch.float64 else fp_forward)(self.handle, image, out, b,
                                                                           stream)
         return out
@@ -277,9 +287,7 @@ class Geometry:
         """A^T y for float32 (production kernels) or float64 (FP64 kernels)."""
         import torch
         b = self._batch(sino, (self.n_views, self.n_det), "sino")
-        if out is None:
-            shape = (self.ny, self.nx) if sino.dim() == 2 else (b, self.ny, self.nx)
-            out = torch.empty(shape, dtype=sino.dtype, device=sino.device)
+        out = self._output(out, sino, b, (self.ny, self.nx), sino.dtype, "out")
         (fp_back_f64 if sino.dtype == torch.float64 else fp_back)(self.handle, sino, out, b, stream)
         return out
 
@@ -287,9 +295,7 @@ class Geometry:
         """The exact reference projection (FP64) of an image or a batch."""
         import torch
         b = self._batch(image, (self.ny, self.nx), "image")
-        if out is None:
-            shape = (self.n_views, self.n_det) if image.dim() == 2 else (b, self.n_views, self.n_det)
-            out = torch.empty(shape, dtype=torch.float64, device=image.device)
+        out = self._output(out, image, b, (self.n_views, self.n_det), torch.float64, "out")
         fp_forward_reference(self.handle, image, out, b, quad_points, stream)
         return out
 
@@ -297,17 +303,16 @@ class Geometry:
         """The adjoint of forward_reference (FP64)."""
         import torch
         b = self._batch(sino, (self.n_views, self.n_det), "sino")
-        if out is None:
-            shape = (self.ny, self.nx) if sino.dim() == 2 else (b, self.ny, self.nx)
-            out = torch.empty(shape, dtype=torch.float64, device=sino.device)
+        out = self._output(out, sino, b, (self.ny, self.nx), torch.float64, "out")
         fp_back_reference(self.handle, sino, out, b, quad_points, stream)
         return out
 
     def sirt_step(self, image, sino_meas, relaxation=1.0, work=None, stream=None):
         import torch
         b = self._batch(image, (self.ny, self.nx), "image")
-        if work is None:
-            work = torch.empty_like(sino_meas)
+        if self._batch(sino_meas, (self.n_views, self.n_det), "sino_meas") != b:
+            raise ValueError("sino_meas and image hold different batch sizes")
+        work = self._output(work, image, b, (self.n_views, self.n_det), torch.float32, "work")
         fp_sirt_step(self.handle, image, sino_meas, relaxation, work, b, stream)
         return image
 
