@@ -446,7 +446,7 @@ struct BackStage {
     // per-thread share of one view's staged cells (prefetched into registers)
     static constexpr int kPer = (CAP + kBackThreads - 1) / kBackThreads;
     Real invr[kPer], ghr[kPer], hab[kPer], ia[kPer], nhbia[kPer], ha[kPer], w[kPer][NB];
-    int4 tc;   // tile entry of the view: M0, cnt, T, H bits
+    int4 tc;   // tile entry of the view: M0, cnt, T, window constant (float bits)
 };
 
 template <typename Real, int NB, int CAP>
@@ -614,7 +614,8 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
     const double ystep = kRowStep * G.pixel;
     const double D = G.dsd, step = G.cell_step, c0 = 0.5 * (G.nd - 1);
     const Real Dr = (Real)D, stepr = (Real)step;
-    const float istep = (float)(1.0 / step), c0f = (float)c0;
+    const float istep = (float)(1.0 / step);
+    const float Distep = (float)(D / step);
 
     Real acc[P][NB];
 #pragma unroll
@@ -641,8 +642,11 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
         for (int v = vb; v < ve; ++v) {
             const int4 tc = st.tc;
             const int M0 = tc.x, cnt = tc.y, T = tc.z;
-            const float H = __int_as_float(tc.w);
-            const BackLds<Real, NB, CAP> &l = lds[v & 1];
+            const float wc = __int_as_float(tc.w);
+            // (buffer offset formed in scalar registers: v is uniform)
+            const BackLds<Real, NB, CAP> &l = *reinterpret_cast<const BackLds<Real, NB, CAP> *>(
+                reinterpret_cast<const char *>(&lds[0]) +
+                __builtin_amdgcn_readfirstlane((v & 1) * (int)sizeof(BackLds<Real, NB, CAP>)));
             if (v + 1 < v_end)
                 back_prefetch<Real, NB, CAP, MODE>(G, tab, sino, v + 1, tile, ntiles, nrays, st);
 
@@ -651,26 +655,29 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                 double ek = xk * cs.y - yk0 * cs.x;             // e . k
                 double h = G.dsc - (xk * cs.x + yk0 * cs.y);    // D_sc - u . k
                 const double dek = -ystep * cs.x, dh = -ystep * cs.y;
+                // Window start in staged cells: w0 = m_lo - (M0 - kBackPad) with
+                // m_lo = ceil((c_k - H) / step + c0), H the tile's bound on
+                // |c_k - c_m| over non-zero cells, clamped to the staged range;
+                // the tile table folds the constants into wc, so per pixel it
+                // is ceil(c_k / step + wc).
+                const int base = M0 - kBackPad;
+                const int w_hi = cnt + 2 * kBackPad - min(T, cnt + 2 * kBackPad);
+                const int Tw = T <= kBackMaxUnrolled ? T : min(T, cnt + 2 * kBackPad);
 #pragma unroll
                 for (int p = 0; p < P; ++p, ek += dek, h += dh) {
-                    // the pixel's window: m_lo = ceil((c_k - H) / step + c0)
-                    // with c_k the pixel's coordinate (flat: its shadow
+                    // the pixel's coordinate c_k (flat: its shadow
                     // s_k = D (e.k) / h; parallel: e.k; arc: its angle
-                    // atan(e.k / h)), shifted (never past a non-zero cell) so
-                    // that it stays inside the staged cells
+                    // atan(e.k / h)); the window never passes a non-zero cell
                     const float hf = (float)h, ekf = (float)ek;
-                    float ck;
+                    float wf;
                     if constexpr (BEAM == FP_PARALLEL)
-                        ck = ekf;
+                        wf = fmaf(ekf, istep, wc);
                     else if constexpr (BEAM == FP_FAN_ARC)
-                        ck = atanf(ekf * fast_rcp(hf));
+                        wf = fmaf(atanf(ekf * fast_rcp(hf)), istep, wc);
                     else
-                        ck = (float)D * ekf * fast_rcp(hf);
-                    const int m_lo = (int)ceilf(fmaf(ck - H, istep, c0f));
-                    const int w0 = min(max(m_lo - M0 + kBackPad, 0),
-                                       cnt + 2 * kBackPad - min(T, cnt + 2 * kBackPad));
-                    const int m_first = M0 - kBackPad + w0;
-                    const int Tw = T <= kBackMaxUnrolled ? T : min(T, cnt + 2 * kBackPad);
+                        wf = fmaf(Distep * ekf, fast_rcp(hf), wc);
+                    const int w0 = min(max((int)ceilf(wf), 0), w_hi);
+                    const int m_first = base + w0;
                     Real part[NB];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) part[b] = 0;
@@ -684,7 +691,7 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                         // ln = D h + s_m (e.k) (parallel: num = e.k - s_m,
                         // ln = 1), at the window's first cell in FP64, then
                         // steps of one cell
-                        const double s_first = (m_first - c0) * step;
+                        const double s_first = fma((double)m_first, step, -c0 * step);
                         Real num0, dnum, ln0, dln;
                         if constexpr (BEAM == FP_PARALLEL) {
                             num0 = (Real)(ek - s_first);

@@ -110,7 +110,8 @@ __device__ double pmax_interval(double p0, double p1) {
 // smallest depth and hab = delta P(psi) / 2 at the direction psi of w_perp.
 //
 // The window of every pixel of the tile then holds T = floor(2 H / step) + 1
-// cells, step the cell spacing in the same coordinate.
+// cells, step the cell spacing in the same coordinate; the table stores the
+// constant that places it (see below) rather than H.
 __global__ __launch_bounds__(256) void tile_table_kernel(const double2 *__restrict__ views,
                                                          TileTableArgs a,
                                                          int4 *__restrict__ out,
@@ -180,14 +181,20 @@ __global__ __launch_bounds__(256) void tile_table_kernel(const double2 *__restri
         H = (delta * Pmax / (2.0 * hmin) + 0.5 * kappa * tau) / den;
         ok = den > 0.0;
     }
-    // margin for the FP32 coordinate and window start computed per pixel
+    // margin for the FP32 coordinate and window start computed per pixel,
+    // including the FP32 rounding of the window constant below
+    const int M0 = cnt ? (int)lo : 0;
+    const double rel = (double)M0 - kBackPad - c0;   // staged cell 0 from the centre, in cells
     H = H * (1.0 + 1e-5) + 1e-3 * step + 1e-6 * fmax(fabs(smin), fabs(smax)) +
-        (beam == FP_FAN_ARC ? 1e-7 : 0.0);
+        (beam == FP_FAN_ARC ? 1e-7 : 0.0) + ldexp(fabs(rel) + 1.0, -21) * step;
     // (capped far above any staged range; the kernel clamps a window to the
     // staged cells, which hold every non-zero cell)
     const double Td = floor(2.0 * H / step) + 1.0;
     const int T = ok && Td < (double)(1 << 20) ? (int)Td : (1 << 20);
-    out[t] = make_int4(cnt ? (int)lo : 0, cnt, T, __float_as_int((float)H));
+    // A pixel with coordinate c_k starts its window at staged cell
+    // ceil((c_k - H) / step + c0) - (M0 - kBackPad) = ceil(c_k / step + wc).
+    const float wc = (float)(-H / step - rel);
+    out[t] = make_int4(M0, cnt, T, __float_as_int(wc));
     atomicMax(&maxima[0], cnt);
     atomicMax(&maxima[1], T);
 }
