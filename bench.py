@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "b04b2a99a723a2ad4be5a88482bd1da82ff3af7b4e719230a8b169b2ef5b99fd",
-    "bytes_per_launch": {"forward": 36006279, "back": 231962042},
+    "sources_sha256": "519886113028051cead7bd7c504db12116deadf649ee629541e1cf119543d6fb",
+    "bytes_per_launch": {"forward": 36005693, "back": 232275566},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",

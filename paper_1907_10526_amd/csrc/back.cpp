@@ -7,9 +7,9 @@ namespace fanproj {
 template <typename Real>
 int back_max_batch(const DevGeom &g) {
     if (g.back_cap <= 0) return 0;
-    // two LDS buffers of (kBackRayParams + nb) arrays of back_cap values
+    // two LDS buffers of back_lds_values(nb) arrays of back_cap values
     for (int nb = kMaxBatchChunk; nb >= 1; nb /= 2)
-        if (2 * (size_t)(kBackRayParams + nb) * g.back_cap * sizeof(Real) <= kBackLdsLimit) return nb;
+        if (2 * (size_t)back_lds_values(nb) * g.back_cap * sizeof(Real) <= kBackLdsLimit) return nb;
     return 0;
 }
 

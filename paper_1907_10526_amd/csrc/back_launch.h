@@ -12,7 +12,7 @@ namespace {
 
 template <typename Real, int NB, int CAP>
 constexpr bool back_fits() {
-    return 2 * (size_t)(kBackRayParams + NB) * CAP * sizeof(Real) <= kBackLdsLimit;
+    return 2 * (size_t)back_lds_values(NB) * CAP * sizeof(Real) <= kBackLdsLimit;
 }
 
 template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>

@@ -37,8 +37,11 @@ constexpr int kBackRayParams = 6;
 constexpr int kBackPad = 8;
 // Widest per-tile window with an unrolled cell loop.
 constexpr int kBackMaxUnrolled = 8;
+// Values staged per cell by the back projection for a batch chunk of nb
+// images: the per-ray parameters and the weights, padded to pairs.
+constexpr int back_lds_values(int nb) { return kBackRayParams + 2 * ((nb + 1) / 2); }
 // Cell capacities (per view and tile) the back projection is instantiated for;
-// the LDS then holds (kBackRayParams + batch) arrays of that many values.
+// the LDS then holds back_lds_values(batch) arrays of that many values.
 constexpr int kBackCaps[] = {64, 128, 256, 512, 1024};
 constexpr int kBackMaxCap = 1024;
 // LDS the back kernel may use per work-group (two staging buffers).

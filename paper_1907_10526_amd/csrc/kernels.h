@@ -449,10 +449,32 @@ struct BackStage {
     int4 tc;   // tile entry of the view: M0, cnt, T, window constant (float bits)
 };
 
+// Two-component vector of the arithmetic type (float2 / double2).
+template <typename Real>
+struct Pair;
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+
+// Staged values of cell t as interleaved pairs, so that every value is read
+// with an immediate offset from one base address: (1/R, blur), (hab, 1/a),
+// (-(b-a)/(2a), a/2), then the weights of the batch's images two by two
+// (an odd last one paired with zero).
+constexpr int back_weight_pairs(int nb) { return (nb + 1) / 2; }
+static_assert(3 * 2 == kBackRayParams, "three pairs of per-ray parameters");
 template <typename Real, int NB, int CAP>
 struct BackLds {
-    Real invr[CAP], ghr[CAP], hab[CAP], ia[CAP], nhbia[CAP], ha[CAP], w[NB][CAP];
+    using P2 = typename Pair<Real>::type;
+    P2 rg[CAP], hi[CAP], nh[CAP];
+    P2 w[back_weight_pairs(NB)][CAP];
 };
+static_assert(sizeof(BackLds<float, 1, 64>) == back_lds_values(1) * 64 * sizeof(float),
+              "back-projection staging size");
 
 // Staged cell idx holds cell M0 - kBackPad + idx; the kBackPad cells on either
 // side of [M0, M0 + cnt) get zero weight and harmless constants.
@@ -500,14 +522,28 @@ __device__ __forceinline__ void back_store(const BackStage<Real, NB, CAP> &st,
     for (int k = 0; k < BackStage<Real, NB, CAP>::kPer; ++k) {
         const int idx = (int)threadIdx.x + k * kBackThreads;
         if (idx < n) {
-            l.invr[idx] = st.invr[k];
-            l.ghr[idx] = st.ghr[k];
-            l.hab[idx] = st.hab[k];
-            l.ia[idx] = st.ia[k];
-            l.nhbia[idx] = st.nhbia[k];
-            l.ha[idx] = st.ha[k];
+            l.rg[idx] = {st.invr[k], st.ghr[k]};
+            l.hi[idx] = {st.hab[k], st.ia[k]};
+            l.nh[idx] = {st.nhbia[k], st.ha[k]};
 #pragma unroll
-            for (int b = 0; b < NB; ++b) l.w[b][idx] = st.w[k][b];
+            for (int j = 0; j < back_weight_pairs(NB); ++j)
+                l.w[j][idx] = {st.w[k][2 * j], 2 * j + 1 < NB ? st.w[k][2 * j + 1] : Real(0)};
+        }
+    }
+}
+
+// part[k] += e * (weight of image k at staged cell idx)
+template <typename Real, int NB, int CAP>
+__device__ __forceinline__ void back_accumulate(const BackLds<Real, NB, CAP> &l, int idx, Real e,
+                                                Real (&part)[NB]) {
+#pragma unroll
+    for (int j = 0; j < back_weight_pairs(NB); ++j) {
+        const auto w = l.w[j][idx];
+        part[2 * j] = fma(e, w.x, part[2 * j]);
+        if (2 * j + 1 < NB) {   // resolved at compile time (unrolled)
+            constexpr int kLast = NB - 1;
+            Real &q = part[2 * j + 1 < NB ? 2 * j + 1 : kLast];
+            q = fma(e, w.y, q);
         }
     }
 }
@@ -519,19 +555,16 @@ template <typename Real, int NB, int CAP, bool UNROLLED>
 __device__ __forceinline__ void back_window(const BackLds<Real, NB, CAP> &l, int w0, int T,
                                             Real num0, Real dnum, Real ln0, Real dln,
                                             Real (&part)[NB]) {
-    const Real *invr = l.invr + w0;
-    const Real *ghr = l.ghr + w0;
-    const Real *hab = l.hab + w0;
-    const Real *ia = l.ia + w0;
-    const Real *nhbia = l.nhbia + w0;
-    const Real *ha = l.ha + w0;
+    const auto *rg = l.rg + w0;
+    const auto *hi = l.hi + w0;
+    const auto *nh = l.nh + w0;
     auto entry = [&](int t) {
-        const Real sp = fma(-(Real)t, dnum, num0) * invr[t];
-        const Real hc = fma((Real)t, dln, ln0) * ghr[t];
-        const Trap<Real> p{hab[t], ia[t], nhbia[t], ha[t]};
+        const auto a = rg[t], b = hi[t], c = nh[t];
+        const Real sp = fma(-(Real)t, dnum, num0) * a.x;
+        const Real hc = fma((Real)t, dln, ln0) * a.y;
+        const Trap<Real> p{b.x, b.y, c.x, c.y};
         const Real e = footprint_num(sp, hc, p) * fast_rcp(hc);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) part[b] = fma(e, l.w[b][w0 + t], part[b]);
+        back_accumulate<Real, NB, CAP>(l, w0 + t, e, part);
     };
     if constexpr (UNROLLED) {
 #pragma unroll
@@ -555,17 +588,15 @@ template <typename Real, int NB, int CAP, bool UNROLLED>
 __device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l, const DevGeom &G,
                                                 int w0, int T, int m_first, double ek, double h,
                                                 Real (&part)[NB]) {
-    const Real *ghr = l.ghr + w0;
-    const Real *hab = l.hab + w0;
-    const Real *ia = l.ia + w0;
-    const Real *nhbia = l.nhbia + w0;
-    const Real *ha = l.ha + w0;
+    const auto *rg = l.rg + w0;
+    const auto *hi = l.hi + w0;
+    const auto *nh = l.nh + w0;
     auto entry = [&](int t, Real sp, Real L) {
-        const Real hc = L * ghr[t];
-        const Trap<Real> p{hab[t], ia[t], nhbia[t], ha[t]};
+        const auto b = hi[t], c = nh[t];
+        const Real hc = L * rg[t].y;
+        const Trap<Real> p{b.x, b.y, c.x, c.y};
         const Real e = footprint_num(sp, hc, p) * fast_rcp(hc);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) part[b] = fma(e, l.w[b][w0 + t], part[b]);
+        back_accumulate<Real, NB, CAP>(l, w0 + t, e, part);
     };
     const double2 *cells = G.arc_cells + m_first + kBackPad;
     if constexpr (UNROLLED) {
