@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "519886113028051cead7bd7c504db12116deadf649ee629541e1cf119543d6fb",
-    "bytes_per_launch": {"forward": 36005693, "back": 232275566},
+    "sources_sha256": "402b515218cc9553bd335176e65ac4428695030a1fb979f11b2d531174b55791",
+    "bytes_per_launch": {"forward": 36005506, "back": 232341194},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",

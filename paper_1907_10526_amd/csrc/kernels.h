@@ -171,10 +171,12 @@ __global__ __launch_bounds__(256) void pad_cols_kernel(const Real *__restrict__ 
 // ---------------------------------------------------------------------------
 template <typename Real>
 struct RayWalk {
-    double S;          // s' at cross index 0 of the current row (FP64)
-    double zm, zc;     // s' steps along the march and cross axes
-    double izc;        // 1 / zc
-    double hq;         // half-span of the footprint along the cross axis, pixels
+    // X = 1 - s'(cross index 0) / zc - hq on the current row, in FP64: the
+    // window starts at cross index floor(X), and s' there equals
+    // zc (1 - hq - frac(X))
+    double X, dX;      // and its step per row
+    double zc;         // s' step along the cross axis
+    Real sp_top;       // zc (1 - hq): s' at the window start when frac(X) = 0
     Real zcr;          // zc in the arithmetic type
     Real hcr, dhq, dhr;   // half blur at cross index 0 of the row, and its steps
     Trap<Real> trap;
@@ -199,11 +201,13 @@ __device__ __forceinline__ void walk_rows(RayWalk<Real> &w, int r0, int r1, Real
             // first cross index that can be inside the footprint of this row;
             // clamping keeps the window inside the padded copy (a clamped
             // window lies in the zero margin)
-            int q_lo = (int)floor(fma(-w.S, w.izc, -w.hq)) + 1;
-            q_lo = min(max(q_lo, -kFwdPad), w.nq + kFwdPad - T);
-            const Real sp0 = (Real)fma((double)q_lo, w.zc, w.S);
+            // (a clamped window, and the unclamped one it replaces, lie in
+            // the zero margin: its s' is then immaterial)
+            const double fl = floor(w.X);
+            const int q_lo = min(max((int)fl, -kFwdPad), w.nq + kFwdPad - T);
+            const Real sp0 = fma(-w.zcr, (Real)(w.X - fl), w.sp_top);
             const Real hc0 = fma((Real)q_lo, w.dhq, w.hcr);
-            w.S += w.zm;
+            w.X += w.dX;
             w.hcr += w.dhr;
             Real cv[NB][T];
             if constexpr (kLoad) {
@@ -247,10 +251,11 @@ __device__ void walk_rows_wide(RayWalk<Real> &w, int T, int r0, int r1, Real (&a
 #pragma unroll
         for (int b = 0; b < NB; ++b) blk[b] = 0;
         for (int r = rb; r <= re; ++r, rowp += w.row_stride) {
-            const int q_lo = (int)floor(fma(-w.S, w.izc, -w.hq)) + 1;
-            const Real sp0 = (Real)fma((double)q_lo, w.zc, w.S);
+            const double fl = floor(w.X);
+            const int q_lo = (int)fl;
+            const Real sp0 = fma(-w.zcr, (Real)(w.X - fl), w.sp_top);
             const Real hc0 = fma((Real)q_lo, w.dhq, w.hcr);
-            w.S += w.zm;
+            w.X += w.dX;
             w.hcr += w.dhr;
             for (int t = 0; t < T; ++t) {
                 const int q = q_lo + t;
@@ -340,17 +345,18 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     const int nq = by_rows ? G.nx : G.ny, nr = by_rows ? G.ny : G.nx;
 
     RayWalk<Real> w;
-    w.zc = G.pixel * (by_rows ? wpx : wpy);
-    w.zm = G.pixel * (by_rows ? wpy : wpx);
+    const double zc = G.pixel * (by_rows ? wpx : wpy);
+    const double zm = G.pixel * (by_rows ? wpy : wpx);
     const double lc = G.pixel * (by_rows ? wx : wy);
     const double lm = G.pixel * (by_rows ? wy : wx);
+    w.zc = zc;
     w.trap.hab = tab.hab[ray];
     w.trap.ia = tab.ia[ray];
     w.trap.nhbia = tab.nhbia[ray];
     w.trap.ha = tab.ha[ray];
     w.dhq = (Real)(gR * lc);
     w.dhr = (Real)(gR * lm);
-    w.zcr = (Real)w.zc;
+    w.zcr = (Real)zc;
     w.nq = nq;
     w.nr = nr;
     w.row_stride = (size_t)nq + 2 * kFwdPad;
@@ -360,12 +366,13 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     // Support |s'| < hab + hc, with hc bounded by its value at the far side
     // of the disk containing the image.
     const double hw = (double)w.trap.hab + hc_fix + gR * lmax;
-    w.izc = 1.0 / w.zc;
-    w.hq = hw * fabs(w.izc);
-    const int T = (int)floor(2.0 * w.hq) + 1;   // pixels per row that can be hit
+    const double izc = 1.0 / zc;
+    const double hq = hw * fabs(izc);   // half-span of the footprint along the cross axis
+    const int T = (int)floor(2.0 * hq) + 1;   // pixels per row that can be hit
+    w.sp_top = (Real)(zc * (1.0 - hq));
     // Rows whose window meets [0, nq): qf(r) = qf0 + r dq is the crossing.
-    const double qf0 = -S00 * w.izc, dq = -w.zm * w.izc;
-    const double q_lo_lim = -w.hq - 1.0, q_hi_lim = nq + w.hq;
+    const double qf0 = -S00 * izc, dq = -zm * izc;
+    const double q_lo_lim = -hq - 1.0, q_hi_lim = nq + hq;
     int r_lo = 0, r_hi = nr - 1;
     if (fabs(dq) > 1e-12) {
         double ra = (q_lo_lim - qf0) / dq, rb = (q_hi_lim - qf0) / dq;
@@ -386,7 +393,9 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     int r0 = wave_min(r_lo);
     const int r1 = wave_max(r_hi);
     r0 = max(r0, 0);
-    w.S = S00 + r0 * w.zm;
+    // window start on row r: floor(-s'(0, r) / zc - hq) + 1
+    w.X = 1.0 - hq - (S00 + r0 * zm) * izc;
+    w.dX = -zm * izc;
     w.hcr = (Real)(hc_fix + gR * (L00 + r0 * lm));
 
     Real acc[NB];
