@@ -31,7 +31,7 @@ constexpr int kFwdMaxUnrolled = 8;   // widest row window with an unrolled varia
 constexpr int kMaxBatchChunk = 8;
 // Per-ray parameter arrays staged in LDS by the back-projection kernel, in
 // addition to one sinogram weight array per image.
-constexpr int kBackRayParams = 6;
+constexpr int kBackRayParams = 5;
 // Zero-weight cells staged on each side of a tile's cell range, so that a
 // pixel's fixed-width window never leaves the staged arrays.
 constexpr int kBackPad = 8;
@@ -39,7 +39,9 @@ constexpr int kBackPad = 8;
 constexpr int kBackMaxUnrolled = 8;
 // Values staged per cell by the back projection for a batch chunk of nb
 // images: the per-ray parameters and the weights, padded to pairs.
-constexpr int back_lds_values(int nb) { return kBackRayParams + 2 * ((nb + 1) / 2); }
+constexpr int back_lds_values(int nb) {
+    return kBackRayParams + 1 + 2 * (nb / 2 > 0 ? nb / 2 : 1);
+}
 // Cell capacities (per view and tile) the back projection is instantiated for;
 // the LDS then holds back_lds_values(batch) arrays of that many values.
 constexpr int kBackCaps[] = {64, 128, 256, 512, 1024};
@@ -54,17 +56,35 @@ constexpr int kBackMaxGroups = 8;
 // Per-ray constants, [nv][nd] each, in the kernels' arithmetic type: FP32
 // roundings of FP64 values for the production kernels, the FP64 values
 // themselves for the FP64 instantiation.
+//
+// The back projection evaluates an entry in units scaled by the ray's R_m
+// (flat detector; 1 for the arc detector and parallel beams), where s' R_m
+// and R_m L are its exact numerators: the footprint is homogeneous of degree
+// one in (s', hab, a, hc), so the scaled constants below give R_m times the
+// same value and no per-entry multiplication by 1 / R_m is needed.
+//
+// The kRayTables arrays lie `stride` values apart in one block, in the order
+// of the accessors below.
 template <typename Real>
 struct RayTables {
-    const Real *inv_r = nullptr;  // 1 / R_m,  R_m = |q(s_m) - p|
-    const Real *ghr = nullptr;    // g_m / (2 R_m): half effective blur per unit of R L
-    const Real *hab = nullptr;    // (a + b) / 2, a <= b the projected pixel widths
-    const Real *ia = nullptr;     // 1 / max(a, tiny)
-    const Real *nhbia = nullptr;  // -(b - a) / (2 max(a, tiny))
-    const Real *ha = nullptr;     // a / 2
-    const Real *wb = nullptr;     // delta^2 / (2 b)
+    const Real *base = nullptr;
+    size_t stride = 0;
+    __host__ __device__ const Real *at(int k) const { return base + (size_t)k * stride; }
+    // blur per unit of R L (flat), of L (arc), or tau / 2 (parallel)
+    __host__ __device__ const Real *ghr() const { return at(0); }
+    // (a + b) / 2, a <= b the projected pixel widths
+    __host__ __device__ const Real *hab() const { return at(1); }
+    __host__ __device__ const Real *ia() const { return at(2); }     // 1 / max(a, tiny)
+    // -(b - a) / (2 max(a, tiny))
+    __host__ __device__ const Real *nhbia() const { return at(3); }
+    __host__ __device__ const Real *ha() const { return at(4); }     // a / 2
+    __host__ __device__ const Real *wb() const { return at(5); }     // delta^2 / (2 b)
+    __host__ __device__ const Real *bgh() const { return at(6); }    // ghr R_m
+    __host__ __device__ const Real *bhab() const { return at(7); }   // hab R_m
+    __host__ __device__ const Real *bia() const { return at(8); }    // ia / R_m
+    __host__ __device__ const Real *bha() const { return at(9); }    // ha R_m
 };
-constexpr int kRayTables = 7;
+constexpr int kRayTables = 10;
 
 // Read-only description of a geometry as the kernels see it.  All pointers
 // are device pointers owned by fp_geometry.

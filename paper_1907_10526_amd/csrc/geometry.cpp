@@ -44,8 +44,7 @@ fp_status ensure_f64_tables(fp_geometry *g) {
         g->f64_block = nullptr;
         return device_error("FP64 tables", e);
     }
-    g->dev.r64 = RayTables<double>{ra.f64[0], ra.f64[1], ra.f64[2], ra.f64[3], ra.f64[4],
-                                   ra.f64[5], ra.f64[6]};
+    g->dev.r64 = RayTables<double>{ra.f64[0], per / sizeof(double)};
     g->f64_bytes = bytes;
     g->f64_ready = true;
     return FP_OK;
@@ -168,8 +167,9 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
     const size_t n_arc = beam == FP_FAN_ARC ? (size_t)n_det + 2 * kBackPad : 0;
     size_t off = 0;
     const size_t off_views = off; off = align_up(off + views.size() * sizeof(double), A);
-    size_t off_rays[kRayTables];
-    for (int k = 0; k < kRayTables; ++k) { off_rays[k] = off; off = align_up(off + nr * sizeof(float), A); }
+    // the per-ray tables, equally spaced (RayTables)
+    const size_t ray_per = align_up(nr * sizeof(float), A);
+    const size_t off_rays = off; off += kRayTables * ray_per;
     const size_t off_tiles = off; off = align_up(off + (size_t)n_views * ntiles * sizeof(int4), A);
     const size_t off_arc = off; off = align_up(off + n_arc * sizeof(double2), A);
     const size_t off_rot = off; off = align_up(off + (n_arc ? kBackMaxUnrolled : 0) * sizeof(float2), A);
@@ -198,7 +198,8 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
     RayTableArgs ra{};
     ra.nv = n_views; ra.nd = n_det; ra.beam = beam;
     ra.dsd = D; ra.pitch = pitch; ra.width = tau; ra.pixel = delta;
-    for (int k = 0; k < kRayTables; ++k) ra.f32[k] = reinterpret_cast<float *>(base + off_rays[k]);
+    for (int k = 0; k < kRayTables; ++k)
+        ra.f32[k] = reinterpret_cast<float *>(base + off_rays + k * ray_per);
     e = launch_ray_tables(d_views, ra, nullptr);
     if (e != hipSuccess) return fail("fp_geometry_create: ray tables", e);
     TileTableArgs ta{};
@@ -234,7 +235,7 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
     d.arc_cells = d_arc;
     d.arc_rot = d_rot;
     d.arc_rot64 = d_rot64;
-    d.r32 = RayTables<float>{ra.f32[0], ra.f32[1], ra.f32[2], ra.f32[3], ra.f32[4], ra.f32[5], ra.f32[6]};
+    d.r32 = RayTables<float>{ra.f32[0], ray_per / sizeof(float)};
     d.r64 = RayTables<double>{};
     d.tile_cells = d_tiles;
     d.back_cap = 0;

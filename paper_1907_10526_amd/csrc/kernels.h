@@ -57,6 +57,12 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 __device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+// min(x, c) for finite x, c: the median of x, c and the most negative finite
+// float, which (unlike fmin) takes an operand loaded from memory as it is
+__device__ __forceinline__ float fmin_finite(float x, float c) {
+    return __builtin_amdgcn_fmed3f(x, c, -3.40282347e38f);
+}
+__device__ __forceinline__ double fmin_finite(double x, double c) { return fmin(x, c); }
 
 // Per-ray constants of the trapezoid M_[a,b], a <= b.
 template <typename Real>
@@ -71,7 +77,7 @@ struct Trap {
 // trapezoid.  In FP32 the clamp folds into the FMA's output modifier.
 template <typename Real>
 __device__ __forceinline__ Real gb(Real y, const Trap<Real> &p) {
-    const Real m = fmin(y, p.hab);
+    const Real m = fmin_finite(y, p.hab);
     const Real u = clamp01(fma(m, p.ia, p.nhbia));
     return fma(-p.ha * u, u, m);
 }
@@ -322,12 +328,12 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
             const double2 a = G.arc_cells[m + kBackPad];
             cg = a.x;
             sg = a.y;
-            gR = (double)tab.ghr[ray];                  // tan(tau / (2 D))
+            gR = (double)tab.ghr()[ray];                  // tan(tau / (2 D))
         } else {
             const double R = sqrt(D * D + s * s);
             cg = D / R;
             sg = s / R;
-            gR = (double)tab.ghr[ray] * R;              // g_m / 2
+            gR = (double)tab.ghr()[ray] * R;              // g_m / 2
         }
         wx = -cg * c + sg * sn;
         wy = -cg * sn - sg * c;
@@ -350,10 +356,10 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     const double lc = G.pixel * (by_rows ? wx : wy);
     const double lm = G.pixel * (by_rows ? wy : wx);
     w.zc = zc;
-    w.trap.hab = tab.hab[ray];
-    w.trap.ia = tab.ia[ray];
-    w.trap.nhbia = tab.nhbia[ray];
-    w.trap.ha = tab.ha[ray];
+    w.trap.hab = tab.hab()[ray];
+    w.trap.ia = tab.ia()[ray];
+    w.trap.nhbia = tab.nhbia()[ray];
+    w.trap.ha = tab.ha()[ray];
     w.dhq = (Real)(gR * lc);
     w.dhr = (Real)(gR * lm);
     w.zcr = (Real)zc;
@@ -416,7 +422,7 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
         }
     }
     if (!active) return;
-    const Real wbr = tab.wb[ray];
+    const Real wbr = tab.wb()[ray];
     if constexpr (MODE == FwdMode::kCount) {
         counts[ray] = nonzero;
     } else if constexpr (MODE == FwdMode::kOnes) {
@@ -454,7 +460,7 @@ template <typename Real, int NB, int CAP>
 struct BackStage {
     // per-thread share of one view's staged cells (prefetched into registers)
     static constexpr int kPer = (CAP + kBackThreads - 1) / kBackThreads;
-    Real invr[kPer], ghr[kPer], hab[kPer], ia[kPer], nhbia[kPer], ha[kPer], w[kPer][NB];
+    Real gh[kPer], hab[kPer], ia[kPer], nhbia[kPer], ha[kPer], w[kPer][NB];
     int4 tc;   // tile entry of the view: M0, cnt, T, window constant (float bits)
 };
 
@@ -471,16 +477,16 @@ struct Pair<double> {
 };
 
 // Staged values of cell t as interleaved pairs, so that every value is read
-// with an immediate offset from one base address: (1/R, blur), (hab, 1/a),
-// (-(b-a)/(2a), a/2), then the weights of the batch's images two by two
-// (an odd last one paired with zero).
-constexpr int back_weight_pairs(int nb) { return (nb + 1) / 2; }
-static_assert(3 * 2 == kBackRayParams, "three pairs of per-ray parameters");
+// with an immediate offset from one base address: (blur, hab), (1/a,
+// -(b-a)/(2a)), (a/2, weight of image 0), then the other images' weights two
+// by two (an odd last one paired with zero); all scaled as the back tables.
+constexpr int back_weight_pairs(int nb) { return nb / 2; }
+static_assert(5 == kBackRayParams, "five per-ray parameters");
 template <typename Real, int NB, int CAP>
 struct BackLds {
     using P2 = typename Pair<Real>::type;
-    P2 rg[CAP], hi[CAP], nh[CAP];
-    P2 w[back_weight_pairs(NB)][CAP];
+    P2 gh_hab[CAP], ia_nhbia[CAP], ha_w0[CAP];
+    P2 w[back_weight_pairs(NB) > 0 ? back_weight_pairs(NB) : 1][CAP];
 };
 static_assert(sizeof(BackLds<float, 1, 64>) == back_lds_values(1) * 64 * sizeof(float),
               "back-projection staging size");
@@ -500,19 +506,17 @@ __device__ __forceinline__ void back_prefetch(const DevGeom &G, const RayTables<
         const int c = idx - kBackPad;
         if (c >= 0 && c < cnt) {
             const size_t r = (size_t)v * G.nd + M0 + c;
-            st.invr[k] = tab.inv_r[r];
-            st.ghr[k] = tab.ghr[r];
-            st.hab[k] = tab.hab[r];
-            st.ia[k] = tab.ia[r];
-            st.nhbia[k] = tab.nhbia[r];
-            st.ha[k] = tab.ha[r];
-            const Real wb = tab.wb[r];
+            st.gh[k] = tab.bgh()[r];
+            st.hab[k] = tab.bhab()[r];
+            st.ia[k] = tab.bia()[r];
+            st.nhbia[k] = tab.nhbia()[r];
+            st.ha[k] = tab.bha()[r];
+            const Real wb = tab.wb()[r];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
                 st.w[k][b] = (MODE == BackMode::kOnes ? Real(1) : sino[b * nrays + r]) * wb;
         } else {
-            st.invr[k] = 0;
-            st.ghr[k] = 1;
+            st.gh[k] = 1;
             st.hab[k] = 1;
             st.ia[k] = 1;
             st.nhbia[k] = 0;
@@ -531,28 +535,30 @@ __device__ __forceinline__ void back_store(const BackStage<Real, NB, CAP> &st,
     for (int k = 0; k < BackStage<Real, NB, CAP>::kPer; ++k) {
         const int idx = (int)threadIdx.x + k * kBackThreads;
         if (idx < n) {
-            l.rg[idx] = {st.invr[k], st.ghr[k]};
-            l.hi[idx] = {st.hab[k], st.ia[k]};
-            l.nh[idx] = {st.nhbia[k], st.ha[k]};
+            l.gh_hab[idx] = {st.gh[k], st.hab[k]};
+            l.ia_nhbia[idx] = {st.ia[k], st.nhbia[k]};
+            l.ha_w0[idx] = {st.ha[k], st.w[k][0]};
 #pragma unroll
             for (int j = 0; j < back_weight_pairs(NB); ++j)
-                l.w[j][idx] = {st.w[k][2 * j], 2 * j + 1 < NB ? st.w[k][2 * j + 1] : Real(0)};
+                l.w[j][idx] = {st.w[k][2 * j + 1], 2 * j + 2 < NB ? st.w[k][2 * j + 2] : Real(0)};
         }
     }
 }
 
-// part[k] += e * (weight of image k at staged cell idx)
+// part[k] += e * (weight of image k at staged cell idx); w0 is image 0's
 template <typename Real, int NB, int CAP>
 __device__ __forceinline__ void back_accumulate(const BackLds<Real, NB, CAP> &l, int idx, Real e,
-                                                Real (&part)[NB]) {
+                                                Real w0, Real (&part)[NB]) {
+    part[0] = fma(e, w0, part[0]);
 #pragma unroll
     for (int j = 0; j < back_weight_pairs(NB); ++j) {
         const auto w = l.w[j][idx];
-        part[2 * j] = fma(e, w.x, part[2 * j]);
-        if (2 * j + 1 < NB) {   // resolved at compile time (unrolled)
-            constexpr int kLast = NB - 1;
-            Real &q = part[2 * j + 1 < NB ? 2 * j + 1 : kLast];
-            q = fma(e, w.y, q);
+        constexpr int kLast = NB - 1;
+        Real &p1 = part[2 * j + 1 <= kLast ? 2 * j + 1 : kLast];
+        p1 = fma(e, w.x, p1);
+        if (2 * j + 2 < NB) {   // resolved at compile time (unrolled)
+            Real &p2 = part[2 * j + 2 <= kLast ? 2 * j + 2 : kLast];
+            p2 = fma(e, w.y, p2);
         }
     }
 }
@@ -564,16 +570,17 @@ template <typename Real, int NB, int CAP, bool UNROLLED>
 __device__ __forceinline__ void back_window(const BackLds<Real, NB, CAP> &l, int w0, int T,
                                             Real num0, Real dnum, Real ln0, Real dln,
                                             Real (&part)[NB]) {
-    const auto *rg = l.rg + w0;
-    const auto *hi = l.hi + w0;
-    const auto *nh = l.nh + w0;
+    const auto *gh_hab = l.gh_hab + w0;
+    const auto *ia_nhbia = l.ia_nhbia + w0;
+    const auto *ha_w0 = l.ha_w0 + w0;
     auto entry = [&](int t) {
-        const auto a = rg[t], b = hi[t], c = nh[t];
-        const Real sp = fma(-(Real)t, dnum, num0) * a.x;
-        const Real hc = fma((Real)t, dln, ln0) * a.y;
-        const Trap<Real> p{b.x, b.y, c.x, c.y};
-        const Real e = footprint_num(sp, hc, p) * fast_rcp(hc);
-        back_accumulate<Real, NB, CAP>(l, w0 + t, e, part);
+        // num = s' R_m and ln = R_m L; the staged constants carry R_m
+        const auto a = gh_hab[t], b = ia_nhbia[t], c = ha_w0[t];
+        const Real num = fma(-(Real)t, dnum, num0);
+        const Real hcR = fma((Real)t, dln, ln0) * a.x;
+        const Trap<Real> p{a.y, b.x, b.y, c.x};
+        const Real e = footprint_num(num, hcR, p) * fast_rcp(hcR);
+        back_accumulate<Real, NB, CAP>(l, w0 + t, e, c.y, part);
     };
     if constexpr (UNROLLED) {
 #pragma unroll
@@ -597,15 +604,15 @@ template <typename Real, int NB, int CAP, bool UNROLLED>
 __device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l, const DevGeom &G,
                                                 int w0, int T, int m_first, double ek, double h,
                                                 Real (&part)[NB]) {
-    const auto *rg = l.rg + w0;
-    const auto *hi = l.hi + w0;
-    const auto *nh = l.nh + w0;
+    const auto *gh_hab = l.gh_hab + w0;
+    const auto *ia_nhbia = l.ia_nhbia + w0;
+    const auto *ha_w0 = l.ha_w0 + w0;
     auto entry = [&](int t, Real sp, Real L) {
-        const auto b = hi[t], c = nh[t];
-        const Real hc = L * rg[t].y;
-        const Trap<Real> p{b.x, b.y, c.x, c.y};
+        const auto a = gh_hab[t], b = ia_nhbia[t], c = ha_w0[t];
+        const Real hc = L * a.x;
+        const Trap<Real> p{a.y, b.x, b.y, c.x};
         const Real e = footprint_num(sp, hc, p) * fast_rcp(hc);
-        back_accumulate<Real, NB, CAP>(l, w0 + t, e, part);
+        back_accumulate<Real, NB, CAP>(l, w0 + t, e, c.y, part);
     };
     const double2 *cells = G.arc_cells + m_first + kBackPad;
     if constexpr (UNROLLED) {

@@ -9,7 +9,9 @@ namespace fanproj {
 namespace {
 
 // Unit normal w_perp of the ray of cell m (w rotated by +90 degrees, w from
-// the source towards the detector), the blur constant ghr and 1/R.
+// the source towards the detector), the blur constant ghr and 1/R.  The back
+// projection's tables are these constants in units of R for the flat
+// detector (its s' R and R L are exact numerators, see RayTables).
 //   flat:     w_perp = (D e + s u) / R, R = sqrt(D^2 + s^2); eq. (17) gives
 //             tau' = g L with g = (tau/2) D [1/(D^2 + s(s + tau/2)) +
 //             1/(D^2 + s(s - tau/2))], stored as ghr = g / (2R) (the kernels
@@ -59,14 +61,19 @@ __global__ __launch_bounds__(256) void ray_tables_kernel(const double2 *__restri
     const double z1 = delta * fabs(f.wpx), z2 = delta * fabs(f.wpy);
     const double lo = fmin(z1, z2), hi = fmax(z1, z2);
     const double a_safe = fmax(lo, 1e-30);
+    // the back projection's scale: R_m for the flat detector, 1 otherwise
+    const double Rs = a.beam == FP_FAN_FLAT ? 1.0 / f.inv_r : 1.0;
     const double val[kRayTables] = {
-        f.inv_r,                       // inv_r
         f.ghr,                         // ghr
         0.5 * (lo + hi),               // hab
         1.0 / a_safe,                  // ia
         -0.5 * (hi - lo) / a_safe,     // nhbia
         0.5 * lo,                      // ha
         delta * delta / (2.0 * hi),    // wb
+        f.ghr * Rs,                    // bgh
+        0.5 * (lo + hi) * Rs,          // bhab
+        1.0 / (a_safe * Rs),           // bia
+        0.5 * lo * Rs,                 // bha
     };
 #pragma unroll
     for (int k = 0; k < kRayTables; ++k) {
