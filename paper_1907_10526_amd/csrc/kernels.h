@@ -229,8 +229,9 @@ __device__ __forceinline__ void walk_rows(RayWalk<Real> &w, int r0, int r1, Real
             }
 #pragma unroll
             for (int t = 0; t < T; ++t) {
-                const Real sp = fma((Real)t, w.zcr, sp0);
-                const Real hc = fma((Real)t, w.dhq, hc0);
+                // (t == 0 spelled out: an FMA by zero does not fold)
+                const Real sp = t == 0 ? sp0 : fma((Real)t, w.zcr, sp0);
+                const Real hc = t == 0 ? hc0 : fma((Real)t, w.dhq, hc0);
                 const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
                 if constexpr (MODE == FwdMode::kCount) {
                     nonzero += (e != Real(0) && cv[0][t] != Real(0));
@@ -573,23 +574,23 @@ __device__ __forceinline__ void back_window(const BackLds<Real, NB, CAP> &l, int
     const auto *gh_hab = l.gh_hab + w0;
     const auto *ia_nhbia = l.ia_nhbia + w0;
     const auto *ha_w0 = l.ha_w0 + w0;
-    auto entry = [&](int t) {
-        // num = s' R_m and ln = R_m L; the staged constants carry R_m
+    // num = s' R_m and ln = R_m L at cell t; the staged constants carry R_m
+    auto entry = [&](int t, Real num, Real ln) {
         const auto a = gh_hab[t], b = ia_nhbia[t], c = ha_w0[t];
-        const Real num = fma(-(Real)t, dnum, num0);
-        const Real hcR = fma((Real)t, dln, ln0) * a.x;
+        const Real hcR = ln * a.x;
         const Trap<Real> p{a.y, b.x, b.y, c.x};
         const Real e = footprint_num(num, hcR, p) * fast_rcp(hcR);
         back_accumulate<Real, NB, CAP>(l, w0 + t, e, c.y, part);
     };
     if constexpr (UNROLLED) {
+        entry(0, num0, ln0);   // (an FMA by zero does not fold)
 #pragma unroll
-        for (int t = 0; t < kBackMaxUnrolled; ++t) {
+        for (int t = 1; t < kBackMaxUnrolled; ++t) {
             if (t >= T) break;  // T is uniform across the work-group
-            entry(t);
+            entry(t, fma(-(Real)t, dnum, num0), fma((Real)t, dln, ln0));
         }
     } else {
-        for (int t = 0; t < T; ++t) entry(t);
+        for (int t = 0; t < T; ++t) entry(t, fma(-(Real)t, dnum, num0), fma((Real)t, dln, ln0));
     }
 }
 
@@ -619,8 +620,9 @@ __device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l,
         const double2 g = cells[0];
         const Real a0 = (Real)(g.x * ek - g.y * h);
         const Real b0 = (Real)(g.x * h + g.y * ek);
+        entry(0, a0, b0);
 #pragma unroll
-        for (int t = 0; t < kBackMaxUnrolled; ++t) {
+        for (int t = 1; t < kBackMaxUnrolled; ++t) {
             if (t >= T) break;  // T is uniform across the work-group
             Real rc, rs;
             arc_rotation<Real>(G, t, rc, rs);
@@ -703,12 +705,14 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                 double h = G.dsc - (xk * cs.x + yk0 * cs.y);    // D_sc - u . k
                 const double dek = -ystep * cs.x, dh = -ystep * cs.y;
                 // Window start in staged cells: w0 = m_lo - (M0 - kBackPad) with
-                // m_lo = ceil((c_k - H) / step + c0), H the tile's bound on
-                // |c_k - c_m| over non-zero cells, clamped to the staged range;
-                // the tile table folds the constants into wc, so per pixel it
-                // is ceil(c_k / step + wc).
+                // m_lo = floor((c_k - H) / step + c0) + 1, H the tile's bound on
+                // |c_k - c_m| over non-zero cells (the first cell past
+                // c_k - H), clamped to the staged range; the tile table folds
+                // the constants into wc, so per pixel it is the integer part
+                // of c_k / step + wc clamped to [0, w_hi].
                 const int base = M0 - kBackPad;
                 const int w_hi = cnt + 2 * kBackPad - min(T, cnt + 2 * kBackPad);
+                const float w_hif = (float)w_hi;
                 const int Tw = T <= kBackMaxUnrolled ? T : min(T, cnt + 2 * kBackPad);
 #pragma unroll
                 for (int p = 0; p < P; ++p, ek += dek, h += dh) {
@@ -723,7 +727,7 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                         wf = fmaf(atanf(ekf * fast_rcp(hf)), istep, wc);
                     else
                         wf = fmaf(Distep * ekf, fast_rcp(hf), wc);
-                    const int w0 = min(max((int)ceilf(wf), 0), w_hi);
+                    const int w0 = (int)__builtin_amdgcn_fmed3f(wf, 0.0f, w_hif);
                     const int m_first = base + w0;
                     Real part[NB];
 #pragma unroll

@@ -193,14 +193,15 @@ __global__ __launch_bounds__(256) void tile_table_kernel(const double2 *__restri
     const int M0 = cnt ? (int)lo : 0;
     const double rel = (double)M0 - kBackPad - c0;   // staged cell 0 from the centre, in cells
     H = H * (1.0 + 1e-5) + 1e-3 * step + 1e-6 * fmax(fabs(smin), fabs(smax)) +
-        (beam == FP_FAN_ARC ? 1e-7 : 0.0) + ldexp(fabs(rel) + 1.0, -21) * step;
+        (beam == FP_FAN_ARC ? 1e-7 : 0.0) + ldexp(fabs(rel) + 2.0, -21) * step;
     // (capped far above any staged range; the kernel clamps a window to the
     // staged cells, which hold every non-zero cell)
     const double Td = floor(2.0 * H / step) + 1.0;
     const int T = ok && Td < (double)(1 << 20) ? (int)Td : (1 << 20);
     // A pixel with coordinate c_k starts its window at staged cell
-    // ceil((c_k - H) / step + c0) - (M0 - kBackPad) = ceil(c_k / step + wc).
-    const float wc = (float)(-H / step - rel);
+    // floor((c_k - H) / step + c0) + 1 - (M0 - kBackPad) = floor(c_k / step + wc):
+    // the first cell past c_k - H, and every non-zero cell lies past it.
+    const float wc = (float)(-H / step - rel + 1.0);
     out[t] = make_int4(M0, cnt, T, __float_as_int(wc));
     atomicMax(&maxima[0], cnt);
     atomicMax(&maxima[1], T);
