@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "0c3b2845c164fbc6f870cc997b5cc182f1af9c5b6da5a6eb233ea94bc0b23381",
-    "bytes_per_launch": {"forward": 36008312, "back": 208398112},
+    "sources_sha256": "9b0dd293ec67f781727128720129ff2207f1b0562d890e25d2d53845de41b50c",
+    "bytes_per_launch": {"forward": 36015624, "back": 197896391},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",

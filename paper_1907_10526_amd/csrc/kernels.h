@@ -47,6 +47,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fanproj_internal.h"
 
@@ -193,39 +194,94 @@ struct RayWalk {
     size_t img_stride; // values between images of the copy
 };
 
+// Row stepper of walk_rows.  FP64 (the FP64 instantiation): X itself.
+// FP32: X + kFwdPad in 32.32 fixed point, re-anchored from the FP64 X at the
+// start of every block of kSumBlock rows (so its drift stays below
+// kSumBlock * 2^-33 pixel); one 64-bit integer add per row, the high word is
+// the padded cross index of the window start and the low word its fraction.
+template <typename Real>
+struct RowStepper {
+    double X;
+    __device__ void start(double X0) { X = X0; }
+    // padded window start p (clamped to [0, p_max]) and fraction of X
+    __device__ __forceinline__ void row(unsigned p_max, unsigned &p, Real &frac) {
+        const double fl = floor(X);
+        const int q = (int)fl;
+        p = (unsigned)min(max(q, -kFwdPad), (int)p_max - kFwdPad) + kFwdPad;
+        frac = (Real)(X - fl);
+    }
+    __device__ __forceinline__ void next(double dX) { X += dX; }
+};
+template <>
+struct RowStepper<float> {
+    double X;              // FP64 X at the start of the block
+    unsigned lo, hi;       // X + kFwdPad in 32.32 fixed point (hi signed)
+    unsigned dlo, dhi;     // its step per row
+    __device__ void start(double X0) { X = X0; }
+    __device__ void anchor(double dX) {
+        const double xb = X + kFwdPad, fl = floor(xb);
+        hi = (unsigned)(int)fl;
+        lo = (unsigned)((xb - fl) * 4294967296.0);
+        const long long d = (long long)rint(dX * 4294967296.0);   // |dX| <= 1
+        dlo = (unsigned)d;
+        dhi = (unsigned)(d >> 32);
+    }
+    // (a negative X + kFwdPad wraps to a large unsigned value and clamps to
+    // p_max, a window in the zero margin on the far side)
+    __device__ __forceinline__ void row(unsigned p_max, unsigned &p, float &frac) {
+        p = min(hi, p_max);
+        frac = (float)lo;   // the fraction in units of 2^-32
+    }
+    __device__ __forceinline__ void next(double) {
+        const unsigned l = lo + dlo;
+        hi += dhi + (l < lo ? 1u : 0u);
+        lo = l;
+    }
+};
+
 template <typename Real, int NB, int T, FwdMode MODE>
 __device__ __forceinline__ void walk_rows(RayWalk<Real> &w, int r0, int r1, Real (&acc)[NB],
                                           int &nonzero) {
     constexpr bool kLoad = MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual;
-    const Real *rowp = w.base + (size_t)r0 * w.row_stride;
+    constexpr bool kFixed = std::is_same<Real, float>::value;
+    // the window start, clamped so that the window stays inside the padded
+    // copy (a clamped window, and the unclamped one it replaces, lie in the
+    // zero margin: its s' is then immaterial)
+    const unsigned p_max = (unsigned)(w.nq + 2 * kFwdPad - T);
+    // s' at the window start is zc (1 - hq - frac(X)); in fixed point frac
+    // arrives in units of 2^-32
+    const Real zfrac = kFixed ? -w.zcr * Real(2.3283064365386963e-10) : -w.zcr;
+    // half blur at padded cross index 0 of the row
+    Real hcp = fma(-(Real)kFwdPad, w.dhq, w.hcr);
+    const Real *rowp = w.base - kFwdPad + (size_t)r0 * w.row_stride;
+    RowStepper<Real> X;
+    X.start(w.X);
     for (int rb = r0; rb <= r1; rb += kSumBlock) {
         const int re = min(rb + kSumBlock - 1, r1);
+        if constexpr (kFixed) X.anchor(w.dX);
         Real blk[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) blk[b] = 0;
         for (int r = rb; r <= re; ++r, rowp += w.row_stride) {
-            // first cross index that can be inside the footprint of this row;
-            // clamping keeps the window inside the padded copy (a clamped
-            // window lies in the zero margin)
-            // (a clamped window, and the unclamped one it replaces, lie in
-            // the zero margin: its s' is then immaterial)
-            const double fl = floor(w.X);
-            const int q_lo = min(max((int)fl, -kFwdPad), w.nq + kFwdPad - T);
-            const Real sp0 = fma(-w.zcr, (Real)(w.X - fl), w.sp_top);
-            const Real hc0 = fma((Real)q_lo, w.dhq, w.hcr);
-            w.X += w.dX;
-            w.hcr += w.dhr;
+            unsigned p;
+            Real frac;
+            X.row(p_max, p, frac);
+            const Real sp0 = fma(zfrac, frac, w.sp_top);
+            const Real hc0 = fma((Real)p, w.dhq, hcp);
+            hcp += w.dhr;
             Real cv[NB][T];
             if constexpr (kLoad) {
-                const Real *p = rowp + q_lo;
+                const Real *pp = reinterpret_cast<const Real *>(
+                    reinterpret_cast<const char *>(rowp) + (p * (unsigned)sizeof(Real)));
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
-                    for (int t = 0; t < T; ++t) cv[b][t] = p[b * w.img_stride + t];
+                    for (int t = 0; t < T; ++t) cv[b][t] = pp[b * w.img_stride + t];
             } else {
 #pragma unroll
                 for (int t = 0; t < T; ++t)
-                    cv[0][t] = ((unsigned)(q_lo + t) < (unsigned)w.nq && r < w.nr) ? Real(1) : Real(0);
+                    cv[0][t] = ((unsigned)((int)p - kFwdPad + t) < (unsigned)w.nq && r < w.nr)
+                                   ? Real(1) : Real(0);
             }
 #pragma unroll
             for (int t = 0; t < T; ++t) {
@@ -240,7 +296,10 @@ __device__ __forceinline__ void walk_rows(RayWalk<Real> &w, int r0, int r1, Real
                     for (int b = 0; b < NB; ++b) blk[b] = fma(e, cv[b][t], blk[b]);
                 }
             }
+            X.next(w.dX);
         }
+        // FP64 X at the next block (fixed point: stepped from this block's start)
+        if constexpr (kFixed) X.X = fma((double)(re - rb + 1), w.dX, X.X);
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[b] += blk[b];
     }
