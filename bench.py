@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "9b0dd293ec67f781727128720129ff2207f1b0562d890e25d2d53845de41b50c",
-    "bytes_per_launch": {"forward": 36015624, "back": 197896391},
+    "sources_sha256": "a653255a69e28da0f15c334e78a8969e220a257604bb40448d637e2940699433",
+    "bytes_per_launch": {"forward": 36014850, "back": 197825039},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",

@@ -560,29 +560,34 @@ __device__ __forceinline__ void back_prefetch(const DevGeom &G, const RayTables<
                                               BackStage<Real, NB, CAP> &st) {
     st.tc = G.tile_cells[(size_t)v * ntiles + tile];
     const int M0 = st.tc.x, cnt = st.tc.y;
+    const int n = cnt > 0 ? cnt + 2 * kBackPad : 0;
+    // ray of the view's cell M0; byte offsets of rays fit 32 bits (fewer than
+    // 2^30 rays), so each table is read from its uniform base plus one
+    // per-lane offset
+    const unsigned ray0 = (unsigned)v * (unsigned)G.nd + (unsigned)M0;
 #pragma unroll
     for (int k = 0; k < BackStage<Real, NB, CAP>::kPer; ++k) {
         const int idx = (int)threadIdx.x + k * kBackThreads;
-        const int c = idx - kBackPad;
-        if (c >= 0 && c < cnt) {
-            const size_t r = (size_t)v * G.nd + M0 + c;
-            st.gh[k] = tab.bgh()[r];
-            st.hab[k] = tab.bhab()[r];
-            st.ia[k] = tab.bia()[r];
-            st.nhbia[k] = tab.nhbia()[r];
-            st.ha[k] = tab.bha()[r];
-            const Real wb = tab.wb()[r];
+        if (idx < n) {
+            // the padding cells repeat the constants of the nearest cell
+            // (finite entries) with weight zero
+            const int c = idx - kBackPad;
+            const int cc = min(max(c, 0), cnt - 1);
+            const unsigned off = (ray0 + (unsigned)cc) * (unsigned)sizeof(Real);
+            auto at = [off](const Real *base) {
+                return *reinterpret_cast<const Real *>(reinterpret_cast<const char *>(base) + off);
+            };
+            st.gh[k] = at(tab.bgh());
+            st.hab[k] = at(tab.bhab());
+            st.ia[k] = at(tab.bia());
+            st.nhbia[k] = at(tab.nhbia());
+            st.ha[k] = at(tab.bha());
+            const Real wb = at(tab.wb());
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                st.w[k][b] = (MODE == BackMode::kOnes ? Real(1) : sino[b * nrays + r]) * wb;
-        } else {
-            st.gh[k] = 1;
-            st.hab[k] = 1;
-            st.ia[k] = 1;
-            st.nhbia[k] = 0;
-            st.ha[k] = 0;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) st.w[k][b] = 0;
+            for (int b = 0; b < NB; ++b) {
+                const Real w = (MODE == BackMode::kOnes ? Real(1) : at(sino + b * nrays)) * wb;
+                st.w[k][b] = c == cc ? w : Real(0);
+            }
         }
     }
 }
@@ -770,6 +775,8 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                 // the constants into wc, so per pixel it is the integer part
                 // of c_k / step + wc clamped to [0, w_hi].
                 const int base = M0 - kBackPad;
+                // coordinate of staged cell 0
+                const double s_base = ((double)base - c0) * step;
                 const int w_hi = cnt + 2 * kBackPad - min(T, cnt + 2 * kBackPad);
                 const float w_hif = (float)w_hi;
                 const int Tw = T <= kBackMaxUnrolled ? T : min(T, cnt + 2 * kBackPad);
@@ -801,7 +808,7 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                         // ln = D h + s_m (e.k) (parallel: num = e.k - s_m,
                         // ln = 1), at the window's first cell in FP64, then
                         // steps of one cell
-                        const double s_first = fma((double)m_first, step, -c0 * step);
+                        const double s_first = fma((double)w0, step, s_base);
                         Real num0, dnum, ln0, dln;
                         if constexpr (BEAM == FP_PARALLEL) {
                             num0 = (Real)(ek - s_first);
