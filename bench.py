@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "a653255a69e28da0f15c334e78a8969e220a257604bb40448d637e2940699433",
-    "bytes_per_launch": {"forward": 36014850, "back": 197825039},
+    "sources_sha256": "24d0bbec3c525ff09e2324541e6df0bb92fe4bbe9c17731d78cec9b27abcd185",
+    "bytes_per_launch": {"forward": 36016646, "back": 197741728},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",

@@ -610,31 +610,45 @@ __device__ __forceinline__ void back_store(const BackStage<Real, NB, CAP> &st,
     }
 }
 
-// part[k] += e * (weight of image k at staged cell idx); w0 is image 0's
+// part[k] += e * (weight of image k at staged cell idx); w0 is image 0's.
 template <typename Real, int NB, int CAP>
 __device__ __forceinline__ void back_accumulate(const BackLds<Real, NB, CAP> &l, int idx, Real e,
                                                 Real w0, Real (&part)[NB]) {
-    part[0] = fma(e, w0, part[0]);
+    auto acc = [e](Real &p, Real w) { p = fma(e, w, p); };
+    acc(part[0], w0);
 #pragma unroll
     for (int j = 0; j < back_weight_pairs(NB); ++j) {
         const auto w = l.w[j][idx];
         constexpr int kLast = NB - 1;
-        Real &p1 = part[2 * j + 1 <= kLast ? 2 * j + 1 : kLast];
-        p1 = fma(e, w.x, p1);
-        if (2 * j + 2 < NB) {   // resolved at compile time (unrolled)
-            Real &p2 = part[2 * j + 2 <= kLast ? 2 * j + 2 : kLast];
-            p2 = fma(e, w.y, p2);
-        }
+        acc(part[2 * j + 1 <= kLast ? 2 * j + 1 : kLast], w.x);
+        if (2 * j + 2 < NB)   // resolved at compile time (unrolled)
+            acc(part[2 * j + 2 <= kLast ? 2 * j + 2 : kLast], w.y);
     }
 }
 
+// t times the cell spacing for t < kBackMaxUnrolled, held in scalar
+// registers (the spacing is uniform)
+template <typename Real>
+struct CellSteps {
+    Real v[kBackMaxUnrolled];
+    __device__ explicit CellSteps(Real step) {
+#pragma unroll
+        for (int t = 0; t < kBackMaxUnrolled; ++t) v[t] = uniform((Real)t * step);
+    }
+    __device__ static float uniform(float x) {
+        return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+    }
+    __device__ static double uniform(double x) { return x; }
+};
+
 // Entries of one pixel with cells w0 .. w0 + T - 1 of the staged arrays
 // (cell m = M0 - kBackPad + w0 + t).  num0 and ln0 are the numerators of s'
-// and of R L at the first cell; each further cell steps them by -dnum, +dln.
+// and of R L at the first cell; cell t steps them by -t step hn and
+// +t step hl.
 template <typename Real, int NB, int CAP, bool UNROLLED>
 __device__ __forceinline__ void back_window(const BackLds<Real, NB, CAP> &l, int w0, int T,
-                                            Real num0, Real dnum, Real ln0, Real dln,
-                                            Real (&part)[NB]) {
+                                            const CellSteps<Real> &ts, Real stepr, Real num0,
+                                            Real hn, Real ln0, Real hl, Real (&part)[NB]) {
     const auto *gh_hab = l.gh_hab + w0;
     const auto *ia_nhbia = l.ia_nhbia + w0;
     const auto *ha_w0 = l.ha_w0 + w0;
@@ -651,10 +665,13 @@ __device__ __forceinline__ void back_window(const BackLds<Real, NB, CAP> &l, int
 #pragma unroll
         for (int t = 1; t < kBackMaxUnrolled; ++t) {
             if (t >= T) break;  // T is uniform across the work-group
-            entry(t, fma(-(Real)t, dnum, num0), fma((Real)t, dln, ln0));
+            entry(t, fma(-ts.v[t], hn, num0), fma(ts.v[t], hl, ln0));
         }
     } else {
-        for (int t = 0; t < T; ++t) entry(t, fma(-(Real)t, dnum, num0), fma((Real)t, dln, ln0));
+        for (int t = 0; t < T; ++t) {
+            const Real tstep = (Real)t * stepr;
+            entry(t, fma(-tstep, hn, num0), fma(tstep, hl, ln0));
+        }
     }
 }
 
@@ -700,6 +717,11 @@ __device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l,
     }
 }
 
+// Waves per SIMD the back kernel is compiled for: eight (at most 64 VGPRs)
+// for one FP32 image, the occupancy its launch is sized for; no bound for the
+// batched and FP64 variants, which need more registers.
+constexpr int back_min_waves(int nb, size_t real_bytes) { return nb == 1 && real_bytes == 4 ? 8 : 1; }
+
 // One tile (tx, ty) and view group `group` of `groups`.
 template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
 __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], const DevGeom &G,
@@ -729,6 +751,7 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
     const Real Dr = (Real)D, stepr = (Real)step;
     const float istep = (float)(1.0 / step);
     const float Distep = (float)(D / step);
+    const CellSteps<Real> tsteps(stepr);
 
     Real acc[P][NB];
 #pragma unroll
@@ -784,7 +807,8 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                 for (int p = 0; p < P; ++p, ek += dek, h += dh) {
                     // the pixel's coordinate c_k (flat: its shadow
                     // s_k = D (e.k) / h; parallel: e.k; arc: its angle
-                    // atan(e.k / h)); the window never passes a non-zero cell
+                    // atan(e.k / h)); the window never passes a non-zero
+                    // cell
                     const float hf = (float)h, ekf = (float)ek;
                     float wf;
                     if constexpr (BEAM == FP_PARALLEL)
@@ -794,41 +818,38 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
                     else
                         wf = fmaf(Distep * ekf, fast_rcp(hf), wc);
                     const int w0 = (int)__builtin_amdgcn_fmed3f(wf, 0.0f, w_hif);
-                    const int m_first = base + w0;
-                    Real part[NB];
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) part[b] = 0;
                     if constexpr (BEAM == FP_FAN_ARC) {
                         if (T <= kBackMaxUnrolled)
-                            back_window_arc<Real, NB, CAP, true>(l, G, w0, Tw, m_first, ek, h, part);
+                            back_window_arc<Real, NB, CAP, true>(l, G, w0, Tw, base + w0, ek, h,
+                                                                 blk[p]);
                         else
-                            back_window_arc<Real, NB, CAP, false>(l, G, w0, Tw, m_first, ek, h, part);
+                            back_window_arc<Real, NB, CAP, false>(l, G, w0, Tw, base + w0, ek,
+                                                                  h, blk[p]);
                     } else {
-                        // s' = num / R_m and R_m L = ln with num = D (e.k) - s_m h,
-                        // ln = D h + s_m (e.k) (parallel: num = e.k - s_m,
-                        // ln = 1), at the window's first cell in FP64, then
-                        // steps of one cell
+                        // s' = num / R_m and R_m L = ln with
+                        // num = D (e.k) - s_m h, ln = D h + s_m (e.k)
+                        // (parallel: num = e.k - s_m, ln = 1), at the
+                        // window's first cell in FP64, then steps of one cell
                         const double s_first = fma((double)w0, step, s_base);
-                        Real num0, dnum, ln0, dln;
+                        Real num0, hn, ln0, hl;
                         if constexpr (BEAM == FP_PARALLEL) {
                             num0 = (Real)(ek - s_first);
-                            dnum = stepr;
+                            hn = Real(1);
                             ln0 = Real(1);
-                            dln = Real(0);
+                            hl = Real(0);
                         } else {
                             num0 = (Real)(D * ek - s_first * h);
-                            const Real hr = (Real)h, ekr = (Real)ek;
-                            ln0 = fma((Real)s_first, ekr, Dr * hr);
-                            dnum = stepr * hr;
-                            dln = stepr * ekr;
+                            hn = (Real)h;
+                            hl = (Real)ek;
+                            ln0 = fma((Real)s_first, hl, Dr * hn);
                         }
                         if (T <= kBackMaxUnrolled)
-                            back_window<Real, NB, CAP, true>(l, w0, Tw, num0, dnum, ln0, dln, part);
+                            back_window<Real, NB, CAP, true>(l, w0, Tw, tsteps, stepr, num0, hn,
+                                                             ln0, hl, blk[p]);
                         else
-                            back_window<Real, NB, CAP, false>(l, w0, Tw, num0, dnum, ln0, dln, part);
+                            back_window<Real, NB, CAP, false>(l, w0, Tw, tsteps, stepr, num0, hn,
+                                                              ln0, hl, blk[p]);
                     }
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) blk[p][b] += part[b];
                 }
             }
             if (v + 1 < v_end) back_store<Real, NB, CAP>(st, lds[(v + 1) & 1]);
@@ -868,7 +889,7 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
 }
 
 template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
-__global__ __launch_bounds__(kBackThreads) void back_kernel(DevGeom G, const Real *__restrict__ sino,
+__global__ __launch_bounds__(kBackThreads, back_min_waves(NB, sizeof(Real))) void back_kernel(DevGeom G, const Real *__restrict__ sino,
                                                             Real *__restrict__ img,
                                                             Real *__restrict__ partial,
                                                             const Real *__restrict__ col_w,
