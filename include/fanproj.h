@@ -224,13 +224,14 @@ typedef struct {
 } fp_sirt_job;
 
 /* One SIRT step for each of n_jobs jobs whose geometries (image size, views,
- * detector cells, distances) may all differ, batched into grouped launches:
- * one launch per phase (padded copies, forward residual, back update) covers
- * up to 12 jobs, every work-group finding its job from the launch's job
- * table.  This is the execution step of continuous batching: a serving loop
- * admits and retires jobs between calls.  The result for each job is that of
- * fp_sirt_step on it alone, up to the order of FP32 summation over view
- * groups.  All geometries must live on one device.  n_jobs == 0 is a no-op. */
+ * detector cells, distances) may all differ.  The padded copies and the
+ * forward residuals of up to 12 jobs run as one launch each, every
+ * work-group finding its job from the launch's job table; each job's back
+ * update then runs as its own launch, split over view groups like
+ * fp_sirt_step's.  This is the execution step of continuous batching: a
+ * serving loop admits and retires jobs between calls.  The result for each
+ * job is that of fp_sirt_step on it alone.  All geometries must live on one
+ * device.  n_jobs == 0 is a no-op. */
 fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs, void *stream);
 
 /* Number of (ray, pixel) pairs with a non-zero entry, counted on the device

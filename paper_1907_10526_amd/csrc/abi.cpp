@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -70,52 +72,74 @@ int chunk_for(int remaining, int max_nb) {
 
 int back_max_chunk(const DevGeom &g) { return std::max(back_max_batch<float>(g), 1); }
 
-// Stream-ordered scratch for the padded image copies of the forward walk:
-// one library-owned memory pool per device that keeps its memory between
-// calls, so concurrent calls on different streams get separate buffers and a
-// steady stream of calls does not reach the driver's allocator.
-std::mutex g_pool_mu;
-std::vector<hipMemPool_t> g_pools;
+// Device scratch of the launches (the forward's padded image copies, the
+// back projection's view-group partials, the grouped SIRT buffers).  Each
+// device keeps a set of buffers for the life of the process.  A call takes a
+// buffer that no other host thread is enqueuing with, makes its stream wait
+// for the buffer's last use (an event recorded on the stream that last used
+// it) and records that event again after its launches, so reuse across
+// calls, streams and threads is ordered on the device with no host
+// synchronisation and no allocation in steady state.  A buffer grows (after
+// its last use has finished) when a call needs more than it holds.
+struct ScratchSlot {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t last = nullptr;
+    bool busy = false;
+};
+std::mutex g_scratch_mu;
+std::vector<std::vector<std::unique_ptr<ScratchSlot>>> g_scratch;   // [device][slot]
 
-hipError_t device_pool(int dev, hipMemPool_t *out) {
-    std::lock_guard<std::mutex> lock(g_pool_mu);
-    if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1, nullptr);
-    if (!g_pools[dev]) {
-        hipMemPoolProps props{};
-        props.allocType = hipMemAllocationTypePinned;
-        props.handleTypes = hipMemHandleTypeNone;
-        props.location.type = hipMemLocationTypeDevice;
-        props.location.id = dev;
-        hipMemPool_t pool = nullptr;
-        hipError_t e = hipMemPoolCreate(&pool, &props);
-        if (e != hipSuccess) return e;
-        uint64_t keep = UINT64_MAX;
-        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        if (e != hipSuccess) return e;
-        g_pools[dev] = pool;
+ScratchSlot *take_slot(int dev, size_t bytes) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
+    ScratchSlot *fit = nullptr, *any = nullptr;
+    for (auto &p : g_scratch[dev]) {
+        if (p->busy) continue;
+        if (p->bytes >= bytes && (!fit || p->bytes < fit->bytes)) fit = p.get();
+        if (!any || p->bytes > any->bytes) any = p.get();
     }
-    *out = g_pools[dev];
-    return hipSuccess;
+    ScratchSlot *s = fit ? fit : any;
+    if (!s) {
+        g_scratch[dev].push_back(std::make_unique<ScratchSlot>());
+        s = g_scratch[dev].back().get();
+    }
+    s->busy = true;
+    return s;
 }
 
-// Scratch buffer freed (stream-ordered) when it goes out of scope.
 class Scratch {
   public:
     Scratch(int dev, size_t bytes, hipStream_t s) : stream_(s) {
-        hipMemPool_t pool = nullptr;
-        err_ = device_pool(dev, &pool);
-        if (err_ == hipSuccess) err_ = hipMallocFromPoolAsync(&ptr_, bytes, pool, s);
-        if (err_ != hipSuccess) ptr_ = nullptr;
+        slot_ = take_slot(dev, bytes);
+        if (!slot_->last) err_ = hipEventCreateWithFlags(&slot_->last, hipEventDisableTiming);
+        if (err_ == hipSuccess && slot_->bytes < bytes) {
+            // grow: wait for the buffer's last use, then replace it
+            err_ = hipEventSynchronize(slot_->last);
+            if (err_ == hipSuccess && slot_->ptr) err_ = hipFree(slot_->ptr);
+            if (err_ == hipSuccess) {
+                slot_->ptr = nullptr;
+                slot_->bytes = 0;
+                err_ = hipMalloc(&slot_->ptr, bytes);
+                if (err_ == hipSuccess) slot_->bytes = bytes;
+                else slot_->ptr = nullptr;
+            }
+        }
+        if (err_ == hipSuccess) err_ = hipStreamWaitEvent(s, slot_->last, 0);
     }
     ~Scratch() {
-        if (ptr_) (void)hipFreeAsync(ptr_, stream_);
+        if (err_ == hipSuccess) (void)hipEventRecord(slot_->last, stream_);
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        slot_->busy = false;
     }
-    float *get() const { return static_cast<float *>(ptr_); }
-    void *raw() const { return ptr_; }
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    float *get() const { return err_ == hipSuccess ? static_cast<float *>(slot_->ptr) : nullptr; }
+    void *raw() const { return err_ == hipSuccess ? slot_->ptr : nullptr; }
     hipError_t status() const { return err_; }
 
   private:
-    void *ptr_ = nullptr;
+    ScratchSlot *slot_ = nullptr;
     hipStream_t stream_;
     hipError_t err_ = hipSuccess;
 };
@@ -430,6 +454,7 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
         if ((st = check_device_ptr(J.work, dev, (tag + " work").c_str())) != FP_OK) return st;
         if ((st = ensure_weights(const_cast<fp_geometry *>(J.geometry), s)) != FP_OK) return st;
         scratch_bytes += (forward_work_bytes<float>(J.geometry->dev, 1) + 255) / 256 * 256;
+        scratch_bytes += (back_work_bytes<float>(J.geometry->dev, 1) + 255) / 256 * 256;
     }
     Scratch scratch(dev, scratch_bytes, s);
     if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step_multi", scratch.status());
@@ -438,7 +463,7 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
     for (int k0 = 0; k0 < n_jobs; k0 += kMaxJobsPerLaunch) {
         MultiArgs args{};
         args.n = std::min(kMaxJobsPerLaunch, n_jobs - k0);
-        unsigned fwd = 0, back = 0;
+        unsigned fwd = 0;
         for (int k = 0; k < args.n; ++k) {
             const fp_sirt_job &J = jobs[k0 + k];
             const fp_geometry *g = J.geometry;
@@ -448,6 +473,8 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
             M.rows = reinterpret_cast<float *>(base + off);
             M.cols = M.rows + (size_t)nrows * (g->nx + 2 * kFwdPad);
             off += (forward_work_bytes<float>(g->dev, 1) + 255) / 256 * 256;
+            M.partial = reinterpret_cast<float *>(base + off);
+            off += (back_work_bytes<float>(g->dev, 1) + 255) / 256 * 256;
             M.image = J.image;
             M.image_out = J.image;
             M.y_meas = J.sino_meas;
@@ -456,12 +483,9 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
             M.col_w = g->col_w;
             M.relaxation = J.relaxation;
             M.fwd_begin = fwd;
-            M.back_begin = back;
             fwd += (unsigned)g->nv * (unsigned)((g->nd + kFwdThreads - 1) / kFwdThreads);
-            back += (unsigned)(g->dev.tiles_x * g->dev.tiles_y);
         }
         args.fwd_blocks = fwd;
-        args.back_blocks = back;
         hipError_t e = launch_sirt_multi(args, s);
         if (e != hipSuccess) return device_error("fp_sirt_step_multi: launch", e);
     }

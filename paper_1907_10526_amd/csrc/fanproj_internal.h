@@ -178,9 +178,10 @@ hipError_t launch_back_beam(const DevGeom &g, BackMode mode, int nb, const Real 
 template <typename Real>
 int back_max_batch(const DevGeom &g);
 
-// Grouped SIRT step: several jobs, each with its own geometry, in one launch
-// per phase (padded copies, forward residual, back update).  Up to
-// kMaxJobsPerLaunch job descriptors travel in the kernel arguments.
+// Grouped SIRT step: several jobs, each with its own geometry; one launch
+// for the padded copies and one for the forward residuals of all of them,
+// then each job's back update.  Up to kMaxJobsPerLaunch job descriptors
+// travel in the kernel arguments.
 constexpr int kMaxJobsPerLaunch = 12;
 struct MultiJob {
     DevGeom g;
@@ -192,16 +193,17 @@ struct MultiJob {
     const float *row_w, *col_w;
     float relaxation;
     unsigned fwd_begin;     // first forward work-group of this job
-    unsigned back_begin;    // first back work-group of this job
+    float *partial;         // view-group partials of the back update (scratch)
 };
 struct MultiArgs {
     int n;
-    unsigned fwd_blocks, back_blocks;
+    unsigned fwd_blocks;
     MultiJob job[kMaxJobsPerLaunch];
 };
 static_assert(sizeof(MultiArgs) <= 4000, "kernel arguments must stay under 4 KB");
 // Launch the three phases for args.job[0 .. n) (multi.hip); rows/cols/
-// fwd_begin/back_begin must be filled in.
+// partial/fwd_begin must be filled in (partial: back_work_bytes<float>(g, 1)
+// bytes).
 hipError_t launch_sirt_multi(const MultiArgs &args, hipStream_t stream);
 
 }  // namespace fanproj

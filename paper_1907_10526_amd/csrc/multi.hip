@@ -1,5 +1,6 @@
-// Grouped SIRT step: the three phases (padded copies, forward residual, back
-// update) of several jobs with different geometries, one launch per phase.
+// Grouped SIRT step of several jobs with different geometries: one launch
+// for the padded copies and one for the forward residuals of all jobs, then
+// each job's back update (which splits its views over work-group groups).
 #include "kernels.h"
 
 namespace fanproj {
@@ -9,10 +10,10 @@ namespace {
 // Grouped SIRT step over several jobs: work-group b of a phase belongs to the
 // last job whose first work-group is <= b (jobs are in order).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int multi_job_of(const MultiArgs &A, unsigned b, bool back) {
+__device__ __forceinline__ int multi_job_of(const MultiArgs &A, unsigned b) {
     int j = 0;
     for (int k = 1; k < A.n; ++k)
-        if ((back ? A.job[k].back_begin : A.job[k].fwd_begin) <= b) j = k;
+        if (A.job[k].fwd_begin <= b) j = k;
     return j;
 }
 
@@ -30,8 +31,8 @@ __global__ __launch_bounds__(256) void pad_multi_kernel(const MultiArgs A) {
         pad_cols_tile<float>(J.image, J.cols, nx, ny, nrows, (t % ti) * 32, (t / ti) * 32, tile);
 }
 
-__global__ __launch_bounds__(kFwdThreads) void forward_multi_kernel(const MultiArgs A) {
-    const int j = multi_job_of(A, blockIdx.x, false);
+__global__ __launch_bounds__(kFwdThreads, 8) void forward_multi_kernel(const MultiArgs A) {
+    const int j = multi_job_of(A, blockIdx.x);
     const MultiJob &J = A.job[j];
     const unsigned local = blockIdx.x - J.fwd_begin;
     const unsigned bx = (J.g.nd + kFwdThreads - 1) / kFwdThreads;
@@ -39,46 +40,22 @@ __global__ __launch_bounds__(kFwdThreads) void forward_multi_kernel(const MultiA
                                                    J.work, nullptr, J.y_meas, J.row_w);
 }
 
-template <int CAP>
-__global__ __launch_bounds__(kBackThreads) void back_multi_kernel(const MultiArgs A) {
-    const int j = multi_job_of(A, blockIdx.x, true);
-    const MultiJob &J = A.job[j];
-    const unsigned local = blockIdx.x - J.back_begin;
-    const int tx = local % J.g.tiles_x, ty = local / J.g.tiles_x;
-    __shared__ BackLds<float, 1, CAP> lds[2];
-    switch (J.g.beam) {
-        case FP_FAN_ARC:
-            back_block<float, 1, CAP, BackMode::kSirtUpdate, FP_FAN_ARC>(
-                lds, J.g, tx, ty, 0, 1, J.work, J.image_out, nullptr, J.col_w, J.relaxation);
-            break;
-        case FP_PARALLEL:
-            back_block<float, 1, CAP, BackMode::kSirtUpdate, FP_PARALLEL>(
-                lds, J.g, tx, ty, 0, 1, J.work, J.image_out, nullptr, J.col_w, J.relaxation);
-            break;
-        default:
-            back_block<float, 1, CAP, BackMode::kSirtUpdate, FP_FAN_FLAT>(
-                lds, J.g, tx, ty, 0, 1, J.work, J.image_out, nullptr, J.col_w, J.relaxation);
-            break;
-    }
-}
-
 }  // namespace
 
 hipError_t launch_sirt_multi(const MultiArgs &A, hipStream_t stream) {
     if (A.n < 1) return hipSuccess;
-    int cap = 0;
-    for (int k = 0; k < A.n; ++k) cap = std::max(cap, A.job[k].g.back_cap);
     hipLaunchKernelGGL(pad_multi_kernel, dim3(64, A.n), dim3(32, 8), 0, stream, A);
     hipLaunchKernelGGL(forward_multi_kernel, dim3(A.fwd_blocks), dim3(kFwdThreads), 0, stream, A);
-    switch (cap) {
-        case 64: hipLaunchKernelGGL(back_multi_kernel<64>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 128: hipLaunchKernelGGL(back_multi_kernel<128>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 256: hipLaunchKernelGGL(back_multi_kernel<256>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 512: hipLaunchKernelGGL(back_multi_kernel<512>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        case 1024: hipLaunchKernelGGL(back_multi_kernel<1024>, dim3(A.back_blocks), dim3(kBackThreads), 0, stream, A); break;
-        default: return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    // The back projection of a small job alone still fills the device with
+    // its view groups; a grouped back kernel, one work-group per tile and
+    // job, measured slower.
+    for (int k = 0; k < A.n && e == hipSuccess; ++k) {
+        const MultiJob &J = A.job[k];
+        e = launch_back<float>(J.g, BackMode::kSirtUpdate, 1, J.work, J.image_out, J.partial,
+                               J.col_w, J.relaxation, stream);
     }
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace fanproj

@@ -11,9 +11,12 @@ arrive over time with different image sizes, view counts and detector counts.
 * an admitted job keeps its geometry tables, iterate, sinogram and scratch on
   the device until it finishes;
 * every step advances admitted jobs by one SIRT iteration in grouped launches
-  (``fp_sirt_step_multi``: one launch per phase for up to 12 jobs of different
-  geometries), so jobs that arrive while others run join at the next step and
-  their work overlaps on the device (continuous batching).  A step takes the
+  (``fp_sirt_step_multi``: the padded copies and forward residuals of up to
+  12 jobs of different geometries in one launch each, then each job's back
+  update), so jobs that arrive while others run join at the next step and
+  their work overlaps on the device (continuous batching).  A job large enough
+  to fill the device by itself runs its iteration with the single-job kernels
+  instead, in the same stream;  A step takes the
   admitted jobs, oldest first, whose summed work per iteration fits a budget
   (always at least the oldest job): enough small jobs to fill the device, without
   stretching an old job's iterations by the work of every younger one;
@@ -85,12 +88,12 @@ def job_iteration_work(spec: JobSpec) -> float:
 
 def job_device_bytes(spec: JobSpec) -> int:
     """Upper estimate of the device memory a job holds while admitted: the
-    FP32 per-ray tables (7 per ray), per-view and per-tile tables, the SIRT
+    FP32 per-ray tables (10 per ray), per-view and per-tile tables, the SIRT
     weights, iterate, sinogram, residual and the padded image copies."""
     rays = spec.n_views * spec.n_det
     pix = spec.n * spec.n
     tiles = math.ceil(spec.n / 16) * math.ceil(spec.n / 32)
-    tables = 4 * 7 * rays + 16 * spec.n_views + 16 * spec.n_views * tiles
+    tables = 4 * 10 * rays + 16 * spec.n_views + 16 * spec.n_views * tiles
     weights = 4 * (rays + pix)
     buffers = 4 * (pix + 2 * rays)
     pad = 4 * spec.n * 2 * (spec.n + 32)
@@ -161,9 +164,10 @@ class Server:
     (``launch`` returning a token and ``wait`` on a token), the loop keeps
     ``depth`` steps in flight: it launches step k + 1 before waiting for step
     k, so the device never idles while the host schedules, and a job's
-    completion time is when the wait on its last step returns.  Releasing a
-    job's geometry synchronises the device, so finished jobs are released
-    when their memory is needed for admission or when nothing is in flight.
+    completion time is when the wait on its last step returns.  A finished
+    job (its last step waited for) is released when its memory is needed for
+    admission or when nothing is in flight; the executor may defer the
+    device-side frees.
     """
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
@@ -216,8 +220,6 @@ class Server:
                 need = job_device_bytes(spec)
                 if (active or inflight or done) and used + need > self.budget:
                     if done:                      # free finished jobs first
-                        while inflight:
-                            retire(*inflight.popleft())
                         release_done()
                         continue
                     break
@@ -264,6 +266,8 @@ class Server:
             if pending and not waiting:
                 clock.wait_until(pending[0].arrival)
         res.makespan = clock.now()
+        if hasattr(self.ex, "flush"):
+            self.ex.flush()
         return res
 
 
@@ -287,6 +291,8 @@ def run_plain(executor, trace, clock=None, keep_outputs: bool = False) -> ServeR
         executor.release(h)
     res.peak_active = 1
     res.makespan = clock.now()
+    if hasattr(executor, "flush"):
+        executor.flush()
     return res
 
 
@@ -304,15 +310,41 @@ def latency_stats(res: ServeResult) -> dict:
 class GpuExecutor:
     """Executor on one GPU through the C ABI: each job gets its own geometry,
     an iterate starting at zero, a seeded sinogram U[0, 4] and a residual
-    buffer, all on the device."""
+    buffer, all on the device.
 
-    def __init__(self, device="cuda"):
+    SIRT steps run on a stream of their own, so preparing a job (building
+    its geometry tables and weights on the default stream, which waits for
+    its own copies) overlaps the steps already queued.  A step runs the jobs
+    whose forward projection has at least `solo_blocks` work-groups of 256
+    rays with the single-job kernels, which also split the back projection
+    over view groups, and groups the others in ``fp_sirt_step_multi``
+    launches.  Released jobs are destroyed `free_batch` at a time: destroying
+    a geometry synchronises the device, once per batch."""
+
+    def __init__(self, device="cuda", solo_blocks: int | None = None, free_batch: int = 16):
         import torch
 
         from . import fanproj
         self.torch = torch
         self.fp = fanproj
         self.device = torch.device(device)
+        if solo_blocks is None:
+            solo_blocks = 8 * torch.cuda.get_device_properties(self.device).multi_processor_count
+        self.solo_blocks = int(solo_blocks)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.free_batch = max(1, int(free_batch))
+        self._released = []
+
+    def _queue(self, handles) -> None:
+        grouped = []
+        for h in handles:
+            g, x, y, w = h
+            if g.n_views * -(-g.n_det // 256) >= self.solo_blocks:
+                g.sirt_step(x, y, 1.0, w)
+            else:
+                grouped.append(h)
+        if grouped:
+            self.fp.fp_sirt_step_multi([(g.handle, x, y, w, 1.0) for g, x, y, w in grouped])
 
     def prepare(self, spec: JobSpec):
         torch = self.torch
@@ -322,17 +354,22 @@ class GpuExecutor:
         x = torch.zeros((g.ny, g.nx), device=self.device)
         w = torch.empty_like(y)
         self.fp.fp_sirt_prepare(g.handle)
+        # the step stream sees the prepared data; the tensors stay allocated
+        # until its work on them is done
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        for t in (x, y, w):
+            t.record_stream(self.stream)
         return (g, x, y, w)
 
     def step(self, handles) -> None:
-        self.fp.fp_sirt_step_multi([(g.handle, x, y, w, 1.0) for g, x, y, w in handles])
-        self.torch.cuda.synchronize(self.device)
+        self.launch(handles).synchronize()
 
     def launch(self, handles):
-        """Queue one grouped SIRT step; returns an event recorded after it."""
-        self.fp.fp_sirt_step_multi([(g.handle, x, y, w, 1.0) for g, x, y, w in handles])
+        """Queue one SIRT step of the jobs; returns an event recorded after it."""
+        with self.torch.cuda.stream(self.stream):
+            self._queue(handles)
         ev = self.torch.cuda.Event()
-        ev.record()
+        ev.record(self.stream)
         return ev
 
     def wait(self, token) -> None:
@@ -340,13 +377,22 @@ class GpuExecutor:
 
     def run_job(self, h, iters: int) -> None:
         g, x, y, w = h
-        for _ in range(iters):
-            g.sirt_step(x, y, 1.0, w)
-        self.torch.cuda.synchronize(self.device)
+        with self.torch.cuda.stream(self.stream):
+            for _ in range(iters):
+                g.sirt_step(x, y, 1.0, w)
+        self.stream.synchronize()
 
     def result(self, h):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return h[1].detach().clone()
 
     def release(self, h) -> None:
-        g = h[0]
-        g.close()
+        self._released.append(h)
+        if len(self._released) >= self.free_batch:
+            self.flush()
+
+    def flush(self) -> None:
+        """Destroy the released jobs' geometries (one device synchronisation)."""
+        for g, *_ in self._released:
+            g.close()
+        self._released.clear()

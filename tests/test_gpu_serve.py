@@ -17,11 +17,14 @@ def torch_cuda():
     return torch
 
 
-def test_results_alone_equal_results_in_the_mix(torch_cuda):
+@pytest.mark.parametrize("solo_blocks", [None, 300])
+def test_results_alone_equal_results_in_the_mix(torch_cuda, solo_blocks):
+    """solo_blocks=300 sends the larger jobs of the mix to the single-job
+    kernels and groups the rest; by default all of these jobs are grouped."""
     torch = torch_cuda
     trace = serve.make_trace(10, rate=200.0, seed=11, sizes=(64, 128, 256), views=(90, 180, 360),
                              iters=6)
-    ex = serve.GpuExecutor()
+    ex = serve.GpuExecutor(solo_blocks=solo_blocks)
     budget = 3 * max(serve.job_device_bytes(s) for s in trace)
     mixed = serve.Server(ex, hbm_budget=budget, keep_outputs=True).run(trace)
     assert mixed.peak_active >= 2 and mixed.peak_bytes <= budget
