@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "24d0bbec3c525ff09e2324541e6df0bb92fe4bbe9c17731d78cec9b27abcd185",
-    "bytes_per_launch": {"forward": 36016646, "back": 197741728},
+    "sources_sha256": "a669a50c4764ba87ca81ec61fb3eec176ef8719415b63c4056434c396f2d75c8",
+    "bytes_per_launch": {"forward": 36015172, "back": 197790460},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",
