@@ -57,6 +57,26 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
+def batched_pairs(geom, img, nb, steps):
+    """Context beside the batch-1 headline: the same pair on nb images at once
+    (the kernels evaluate each entry once for all images of a batch)."""
+    import torch
+    imgs = torch.stack([torch.roll(img, shifts=3 * b, dims=1) for b in range(nb)])
+    sino = geom.forward(imgs)
+    back = geom.back(sino)
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        geom.forward(imgs, out=sino)
+        geom.back(sino, out=back)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    return {"images": nb, "steps": steps, "ms_per_batch": ms, "pairs_per_s": nb / (ms * 1e-3)}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -267,6 +287,8 @@ def main():
         "geometry_create_ms": 1e3 * t_geom,
         "roofline": roofline,
     }
+
+    out["batch8"] = batched_pairs(geom, img, 8, max(2, K // 5))
 
     if args.serve_jobs > 0:
         out["serving"] = serving(args)
