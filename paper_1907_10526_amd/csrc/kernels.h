@@ -94,6 +94,11 @@ __device__ __forceinline__ Real footprint_num(Real sp, Real hc, const Trap<Real>
     return g1 - copysign(g2, y2);
 }
 
+// Waves per SIMD the projection kernels are compiled for: eight (at most 64
+// VGPRs) for one FP32 image, the occupancy their launches are sized for; no
+// bound for the batched and FP64 variants, which need more registers.
+constexpr int min_waves(int nb, size_t real_bytes) { return nb == 1 && real_bytes == 4 ? 8 : 1; }
+
 __device__ __forceinline__ int wave_max(int x) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o));
@@ -178,17 +183,24 @@ __global__ __launch_bounds__(256) void pad_cols_kernel(const Real *__restrict__ 
 // ---------------------------------------------------------------------------
 template <typename Real>
 struct RayWalk {
-    // X = 1 - s'(cross index 0) / zc - hq on the current row, in FP64: the
-    // window starts at cross index floor(X), and s' there equals
-    // zc (1 - hq - frac(X))
-    double X, dX;      // and its step per row
-    double zc;         // s' step along the cross axis
-    Real sp_top;       // zc (1 - hq): s' at the window start when frac(X) = 0
+    // X = 1 - s'(cross index 0) / zc - hq on a row, in FP64: a window of
+    // half span hq starts at cross index floor(X), and s' there equals
+    // zc (1 - hq - frac(X)).  X1 is 1 - s'(cross index 0) / zc on row r0.
+    double X1, dX;     // and its step per row
+    float hq;          // half span of the ray's support along the cross axis
     Real zcr;          // zc in the arithmetic type
-    Real hcr, dhq, dhr;   // half blur at cross index 0 of the row, and its steps
+    Real dhq, dhr;     // steps of the half blur along the cross axis and per row
+    Real hc0, dhc;     // half blur at cross index 0 of row r0, and its step per row
+    // Half span a window on row r needs: (hab + hc_fix + g L) / |zc| with L
+    // the depth of the window's pixels, at most the ray's depth where it
+    // crosses the row plus the window's half extent: hq_row(r) = hqa + hqb
+    // (r - r0), affine in r, capped at hq.  A bound, so FP32 with a relative
+    // margin.
+    float hqa, hqb;
     Trap<Real> trap;
     int nq;            // pixels along the cross axis
     int nr;            // pixels along the march axis
+    int r0;            // first row of the walk
     const Real *base;  // padded copy, cross index 0 of row 0 (image 0)
     size_t row_stride; // values between rows of the copy
     size_t img_stride; // values between images of the copy
@@ -239,9 +251,13 @@ struct RowStepper<float> {
     }
 };
 
+// Rows rb .. re with windows of T pixels.  Xb is X on row rb for the
+// block's half span, whose s' at frac(X) = 0 is sp_top; hcp is the half blur
+// at padded cross index 0 of row rb.  Sums into blk.
 template <typename Real, int NB, int T, FwdMode MODE>
-__device__ __forceinline__ void walk_rows(RayWalk<Real> &w, int r0, int r1, Real (&acc)[NB],
-                                          int &nonzero) {
+__device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Real sp_top,
+                                           Real hcp, int rb, int re, Real (&blk)[NB],
+                                           int &nonzero) {
     constexpr bool kLoad = MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual;
     constexpr bool kFixed = std::is_same<Real, float>::value;
     // the window start, clamped so that the window stays inside the padded
@@ -251,93 +267,113 @@ __device__ __forceinline__ void walk_rows(RayWalk<Real> &w, int r0, int r1, Real
     // s' at the window start is zc (1 - hq - frac(X)); in fixed point frac
     // arrives in units of 2^-32
     const Real zfrac = kFixed ? -w.zcr * Real(2.3283064365386963e-10) : -w.zcr;
-    // half blur at padded cross index 0 of the row
-    Real hcp = fma(-(Real)kFwdPad, w.dhq, w.hcr);
-    const Real *rowp = w.base - kFwdPad + (size_t)r0 * w.row_stride;
+    const Real *rowp = w.base - kFwdPad + (size_t)rb * w.row_stride;
     RowStepper<Real> X;
-    X.start(w.X);
-    for (int rb = r0; rb <= r1; rb += kSumBlock) {
-        const int re = min(rb + kSumBlock - 1, r1);
-        if constexpr (kFixed) X.anchor(w.dX);
-        Real blk[NB];
+    X.start(Xb);
+    if constexpr (kFixed) X.anchor(w.dX);
+    for (int r = rb; r <= re; ++r, rowp += w.row_stride) {
+        unsigned p;
+        Real frac;
+        X.row(p_max, p, frac);
+        const Real sp0 = fma(zfrac, frac, sp_top);
+        const Real hc0 = fma((Real)p, w.dhq, hcp);
+        hcp += w.dhr;
+        Real cv[NB][T];
+        if constexpr (kLoad) {
+            const Real *pp = reinterpret_cast<const Real *>(
+                reinterpret_cast<const char *>(rowp) + (p * (unsigned)sizeof(Real)));
 #pragma unroll
-        for (int b = 0; b < NB; ++b) blk[b] = 0;
-        for (int r = rb; r <= re; ++r, rowp += w.row_stride) {
-            unsigned p;
-            Real frac;
-            X.row(p_max, p, frac);
-            const Real sp0 = fma(zfrac, frac, w.sp_top);
-            const Real hc0 = fma((Real)p, w.dhq, hcp);
-            hcp += w.dhr;
-            Real cv[NB][T];
-            if constexpr (kLoad) {
-                const Real *pp = reinterpret_cast<const Real *>(
-                    reinterpret_cast<const char *>(rowp) + (p * (unsigned)sizeof(Real)));
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
+                for (int t = 0; t < T; ++t) cv[b][t] = pp[b * w.img_stride + t];
+        } else {
 #pragma unroll
-                    for (int t = 0; t < T; ++t) cv[b][t] = pp[b * w.img_stride + t];
+            for (int t = 0; t < T; ++t)
+                cv[0][t] = ((unsigned)((int)p - kFwdPad + t) < (unsigned)w.nq && r < w.nr)
+                               ? Real(1) : Real(0);
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            // (t == 0 spelled out: an FMA by zero does not fold)
+            const Real sp = t == 0 ? sp0 : fma((Real)t, w.zcr, sp0);
+            const Real hc = t == 0 ? hc0 : fma((Real)t, w.dhq, hc0);
+            const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
+            if constexpr (MODE == FwdMode::kCount) {
+                nonzero += (e != Real(0) && cv[0][t] != Real(0));
             } else {
 #pragma unroll
-                for (int t = 0; t < T; ++t)
-                    cv[0][t] = ((unsigned)((int)p - kFwdPad + t) < (unsigned)w.nq && r < w.nr)
-                                   ? Real(1) : Real(0);
+                for (int b = 0; b < NB; ++b) blk[b] = fma(e, cv[b][t], blk[b]);
             }
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                // (t == 0 spelled out: an FMA by zero does not fold)
-                const Real sp = t == 0 ? sp0 : fma((Real)t, w.zcr, sp0);
-                const Real hc = t == 0 ? hc0 : fma((Real)t, w.dhq, hc0);
-                const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
-                if constexpr (MODE == FwdMode::kCount) {
-                    nonzero += (e != Real(0) && cv[0][t] != Real(0));
-                } else {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) blk[b] = fma(e, cv[b][t], blk[b]);
-                }
-            }
-            X.next(w.dX);
         }
-        // FP64 X at the next block (fixed point: stepped from this block's start)
-        if constexpr (kFixed) X.X = fma((double)(re - rb + 1), w.dX, X.X);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] += blk[b];
+        X.next(w.dX);
     }
 }
 
-// Rows whose window is wider than the unrolled variants: same arithmetic,
-// a loop over the window with explicit bounds.
+// Windows wider than the unrolled variants: same arithmetic, a loop over the
+// window with explicit bounds, X in FP64.
 template <typename Real, int NB, FwdMode MODE>
-__device__ void walk_rows_wide(RayWalk<Real> &w, int T, int r0, int r1, Real (&acc)[NB],
-                               int &nonzero) {
-    const Real *rowp = w.base + (size_t)r0 * w.row_stride;
-    for (int rb = r0; rb <= r1; rb += kSumBlock) {
+__device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp_top, Real hcp,
+                                int rb, int re, Real (&blk)[NB], int &nonzero) {
+    const Real *rowp = w.base - kFwdPad + (size_t)rb * w.row_stride;
+    for (int r = rb; r <= re; ++r, rowp += w.row_stride, X += w.dX, hcp += w.dhr) {
+        const double fl = floor(X);
+        const int q_lo = (int)fl;
+        const Real sp0 = fma(-w.zcr, (Real)(X - fl), sp_top);
+        const Real hc0 = fma((Real)(q_lo + kFwdPad), w.dhq, hcp);
+        for (int t = 0; t < T; ++t) {
+            const int q = q_lo + t;
+            if ((unsigned)q >= (unsigned)w.nq || r >= w.nr) continue;
+            const Real sp = fma((Real)t, w.zcr, sp0);
+            const Real hc = fma((Real)t, w.dhq, hc0);
+            const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
+            if constexpr (MODE == FwdMode::kCount) {
+                nonzero += (e != Real(0));
+            } else if constexpr (MODE == FwdMode::kOnes) {
+                blk[0] += e;
+            } else {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    blk[b] = fma(e, rowp[kFwdPad + q + b * w.img_stride], blk[b]);
+            }
+        }
+    }
+}
+
+// The walk over rows r0 .. r1 in blocks of kSumBlock rows.  Each block's
+// window width is the wave's largest need over the block: the blur grows
+// with depth along the ray, so blocks on the source side take narrower
+// windows than the ray's deepest row would.
+template <typename Real, int NB, FwdMode MODE>
+__device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (&acc)[NB],
+                                          int &nonzero) {
+    for (int rb = w.r0; rb <= r1; rb += kSumBlock) {
         const int re = min(rb + kSumBlock - 1, r1);
+        // the block's half span (a lane whose ray misses the block's rows
+        // reads only the zero margin, whatever its window)
+        const float ha = fmaf((float)(rb - w.r0), w.hqb, w.hqa);
+        const float hb = fmaf((float)(re - w.r0), w.hqb, w.hqa);
+        const float hqk = fmaxf(0.0f, fminf(w.hq, fmaxf(ha, hb)));
+        const int Tb = max(wave_max((int)floorf(2.0f * hqk) + 1), 1);
+        const double Xb = fma((double)(rb - w.r0), w.dX, w.X1) - (double)hqk;
+        // (the same hqk in both: X and s' at the window start stay consistent)
+        const Real sp_top = w.zcr * (Real)(1.0 - (double)hqk);
+        // half blur at padded cross index 0 of row rb
+        const Real hcp = fma(-(Real)kFwdPad, w.dhq, fma((Real)(rb - w.r0), w.dhc, w.hc0));
         Real blk[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) blk[b] = 0;
-        for (int r = rb; r <= re; ++r, rowp += w.row_stride) {
-            const double fl = floor(w.X);
-            const int q_lo = (int)fl;
-            const Real sp0 = fma(-w.zcr, (Real)(w.X - fl), w.sp_top);
-            const Real hc0 = fma((Real)q_lo, w.dhq, w.hcr);
-            w.X += w.dX;
-            w.hcr += w.dhr;
-            for (int t = 0; t < T; ++t) {
-                const int q = q_lo + t;
-                if ((unsigned)q >= (unsigned)w.nq || r >= w.nr) continue;
-                const Real sp = fma((Real)t, w.zcr, sp0);
-                const Real hc = fma((Real)t, w.dhq, hc0);
-                const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
-                if constexpr (MODE == FwdMode::kCount) {
-                    nonzero += (e != Real(0));
-                } else if constexpr (MODE == FwdMode::kOnes) {
-                    blk[0] += e;
-                } else {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) blk[b] = fma(e, rowp[q + b * w.img_stride], blk[b]);
-                }
-            }
+        switch (Tb) {
+            case 1:
+            case 2: walk_block<Real, NB, 2, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 3: walk_block<Real, NB, 3, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 4: walk_block<Real, NB, 4, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 5: walk_block<Real, NB, 5, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 6: walk_block<Real, NB, 6, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 7:
+            case 8: walk_block<Real, NB, 8, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            default:
+                walk_block_wide<Real, NB, MODE>(w, Tb, Xb, sp_top, hcp, rb, re, blk, nonzero);
+                break;
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[b] += blk[b];
@@ -415,7 +451,6 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     const double zm = G.pixel * (by_rows ? wpy : wpx);
     const double lc = G.pixel * (by_rows ? wx : wy);
     const double lm = G.pixel * (by_rows ? wy : wx);
-    w.zc = zc;
     w.trap.hab = tab.hab()[ray];
     w.trap.ia = tab.ia()[ray];
     w.trap.nhbia = tab.nhbia()[ray];
@@ -431,11 +466,9 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 
     // Support |s'| < hab + hc, with hc bounded by its value at the far side
     // of the disk containing the image.
-    const double hw = (double)w.trap.hab + hc_fix + gR * lmax;
+    const double hab_c = (double)w.trap.hab + hc_fix;
     const double izc = 1.0 / zc;
-    const double hq = hw * fabs(izc);   // half-span of the footprint along the cross axis
-    const int T = (int)floor(2.0 * hq) + 1;   // pixels per row that can be hit
-    w.sp_top = (Real)(zc * (1.0 - hq));
+    const double hq = fma(gR, lmax, hab_c) * fabs(izc);   // half span along the cross axis
     // Rows whose window meets [0, nq): qf(r) = qf0 + r dq is the crossing.
     const double qf0 = -S00 * izc, dq = -zm * izc;
     const double q_lo_lim = -hq - 1.0, q_hi_lim = nq + hq;
@@ -452,35 +485,34 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     }
     if (r_hi < r_lo) { r_lo = nr; r_hi = -1; }
 
-    // The whole wave walks the union of its rays' rows with one window width:
-    // control flow stays uniform, and rows or pixels outside a ray's own range
-    // read the zero margin or evaluate to zero.
-    const int Tw = wave_max(T);
+    // The whole wave walks the union of its rays' rows, each block of rows
+    // with one window width: control flow stays uniform, and rows or pixels
+    // outside a ray's own range read the zero margin or evaluate to zero.
     int r0 = wave_min(r_lo);
     const int r1 = wave_max(r_hi);
     r0 = max(r0, 0);
+    w.r0 = r0;
+    w.hq = (float)hq * 1.000001f;   // (rounded up)
     // window start on row r: floor(-s'(0, r) / zc - hq) + 1
-    w.X = 1.0 - hq - (S00 + r0 * zm) * izc;
+    w.X1 = 1.0 - (S00 + r0 * zm) * izc;
     w.dX = -zm * izc;
-    w.hcr = (Real)(hc_fix + gR * (L00 + r0 * lm));
+    w.hc0 = (Real)(hc_fix + gR * (L00 + r0 * lm));
+    w.dhc = (Real)(gR * lm);
+    // per-row half spans: hc = hc_fix + gR L, with L at most the depth where
+    // the ray crosses the row, (L00 + qf0 lc) + r (dq lc + lm), plus the
+    // window's half extent (hq + 1) |lc| (parallel beams: gR = 0, hq)
+    {
+        const double L0 = L00 + (qf0 + r0 * dq) * lc + (hq + 1.0) * fabs(lc) + r0 * lm;
+        const double m = 1.0 + 1e-5;   // covers the FP32 rounding of the bound
+        w.hqa = (float)(fma(gR, L0, hab_c) * fabs(izc) * m);
+        w.hqb = (float)(gR * (dq * lc + lm) * fabs(izc) * m);
+    }
 
     Real acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0;
     int nonzero = 0;
-    if (r0 <= r1) {
-        switch (Tw) {
-            case 1:
-            case 2: walk_rows<Real, NB, 2, MODE>(w, r0, r1, acc, nonzero); break;
-            case 3: walk_rows<Real, NB, 3, MODE>(w, r0, r1, acc, nonzero); break;
-            case 4: walk_rows<Real, NB, 4, MODE>(w, r0, r1, acc, nonzero); break;
-            case 5: walk_rows<Real, NB, 5, MODE>(w, r0, r1, acc, nonzero); break;
-            case 6: walk_rows<Real, NB, 6, MODE>(w, r0, r1, acc, nonzero); break;
-            case 7:
-            case 8: walk_rows<Real, NB, 8, MODE>(w, r0, r1, acc, nonzero); break;
-            default: walk_rows_wide<Real, NB, MODE>(w, Tw, r0, r1, acc, nonzero); break;
-        }
-    }
+    if (r0 <= r1) walk_rows<Real, NB, MODE>(w, r1, acc, nonzero);
     if (!active) return;
     const Real wbr = tab.wb()[ray];
     if constexpr (MODE == FwdMode::kCount) {
@@ -502,7 +534,7 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 }
 
 template <typename Real, int NB, FwdMode MODE>
-__global__ __launch_bounds__(kFwdThreads) void forward_kernel(
+__global__ __launch_bounds__(kFwdThreads, min_waves(NB, sizeof(Real))) void forward_kernel(
     DevGeom G, const Real *__restrict__ rows, const Real *__restrict__ cols,
     Real *__restrict__ out, int *__restrict__ counts, const Real *__restrict__ y_meas,
     const Real *__restrict__ row_w) {
@@ -717,11 +749,6 @@ __device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l,
     }
 }
 
-// Waves per SIMD the back kernel is compiled for: eight (at most 64 VGPRs)
-// for one FP32 image, the occupancy its launch is sized for; no bound for the
-// batched and FP64 variants, which need more registers.
-constexpr int back_min_waves(int nb, size_t real_bytes) { return nb == 1 && real_bytes == 4 ? 8 : 1; }
-
 // One tile (tx, ty) and view group `group` of `groups`.
 template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
 __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], const DevGeom &G,
@@ -889,7 +916,7 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
 }
 
 template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
-__global__ __launch_bounds__(kBackThreads, back_min_waves(NB, sizeof(Real))) void back_kernel(DevGeom G, const Real *__restrict__ sino,
+__global__ __launch_bounds__(kBackThreads, min_waves(NB, sizeof(Real))) void back_kernel(DevGeom G, const Real *__restrict__ sino,
                                                             Real *__restrict__ img,
                                                             Real *__restrict__ partial,
                                                             const Real *__restrict__ col_w,
