@@ -235,9 +235,10 @@ typedef struct {
 fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs, void *stream);
 
 /* Number of (ray, pixel) pairs with a non-zero entry, counted on the device
- * with the forward kernel's own enumeration and entry arithmetic; the result
- * is written to *count on return (the call synchronises `stream`).  Used to
- * price the work of a projection. */
+ * over the pixels the forward kernel's windows visit, by the footprint's
+ * support |s'| < (a + b + tau') / 2 (eq. (18)) in FP32; the result is written
+ * to *count on return (the call synchronises `stream`).  Used to price the
+ * work of a projection. */
 fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream);
 
 /* Device bytes held by the geometry: its tables and, once built, the FP64

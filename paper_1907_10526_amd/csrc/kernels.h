@@ -74,24 +74,29 @@ struct Trap {
     Real ha;     // a / 2
 };
 
-// b times the integral over [0, y] (y >= 0) of the centred, unit-mass
-// trapezoid.  In FP32 the clamp folds into the FMA's output modifier.
-template <typename Real>
-__device__ __forceinline__ Real gb(Real y, const Trap<Real> &p) {
-    const Real m = fmin_finite(y, p.hab);
-    const Real u = clamp01(fma(m, p.ia, p.nhbia));
-    return fma(-p.ha * u, u, m);
+// clamp(y, -h, h) for finite y, h >= 0
+__device__ __forceinline__ float clamp_sym(float y, float h) {
+    return __builtin_amdgcn_fmed3f(y, -h, h);
 }
+__device__ __forceinline__ double clamp_sym(double y, double h) { return fmin(fmax(y, -h), h); }
 
 // (2 b hc) * M_[a, b, 2 hc](sp): the blurred footprint up to per-ray and
-// per-entry scale factors.
+// per-entry scale factors.  With G the odd function whose value at y >= 0 is
+// b times the integral over [0, y] of the centred, unit-mass trapezoid,
+//   G(y) = m - (a/2) u^2,  m = clamp(y, -hab, hab),  u = clamp((|m| - h-) / a, 0, 1)
+// for y >= 0 and odd, the footprint is G(x + hc) - G(x - hc), x = |s'|; with
+// both terms together it is (m1 - m2) - (a/2) (u1^2 - sign(x - hc) u2^2).
+// In FP32 the clamps fold into medians and the FMA's output modifier.
 template <typename Real>
 __device__ __forceinline__ Real footprint_num(Real sp, Real hc, const Trap<Real> &p) {
     const Real x = fabs(sp);
     const Real y2 = x - hc;
-    const Real g1 = gb(x + hc, p);
-    const Real g2 = gb(fabs(y2), p);
-    return g1 - copysign(g2, y2);
+    const Real m1 = fmin_finite(x + hc, p.hab);   // x + hc >= 0
+    const Real m2 = clamp_sym(y2, p.hab);
+    const Real u1 = clamp01(fma(m1, p.ia, p.nhbia));
+    const Real u2 = clamp01(fma(fabs(m2), p.ia, p.nhbia));
+    const Real dq = fma(copysign(u2, y2), -u2, u1 * u1);
+    return fma(-p.ha, dq, m1 - m2);
 }
 
 // Waves per SIMD the projection kernels are compiled for: eight (at most 64
@@ -297,10 +302,11 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
             // (t == 0 spelled out: an FMA by zero does not fold)
             const Real sp = t == 0 ? sp0 : fma((Real)t, w.zcr, sp0);
             const Real hc = t == 0 ? hc0 : fma((Real)t, w.dhq, hc0);
-            const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
             if constexpr (MODE == FwdMode::kCount) {
-                nonzero += (e != Real(0) && cv[0][t] != Real(0));
+                // the entry is non-zero on the support |s'| < hab + hc
+                nonzero += (fabs(sp) < w.trap.hab + hc && cv[0][t] != Real(0));
             } else {
+                const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) blk[b] = fma(e, cv[b][t], blk[b]);
             }
@@ -325,10 +331,12 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
             if ((unsigned)q >= (unsigned)w.nq || r >= w.nr) continue;
             const Real sp = fma((Real)t, w.zcr, sp0);
             const Real hc = fma((Real)t, w.dhq, hc0);
-            const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
             if constexpr (MODE == FwdMode::kCount) {
-                nonzero += (e != Real(0));
-            } else if constexpr (MODE == FwdMode::kOnes) {
+                nonzero += (fabs(sp) < w.trap.hab + hc);
+                continue;
+            }
+            const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
+            if constexpr (MODE == FwdMode::kOnes) {
                 blk[0] += e;
             } else {
 #pragma unroll

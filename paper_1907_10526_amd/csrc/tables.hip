@@ -75,10 +75,25 @@ __global__ __launch_bounds__(256) void ray_tables_kernel(const double2 *__restri
         1.0 / (a_safe * Rs),           // bia
         0.5 * lo * Rs,                 // bha
     };
+    // The kernels form u = clamp(m / a + nhbia) with m <= hab, which is 1 in
+    // exact arithmetic at m = hab: nhbia is raised by the few ulps that make
+    // the rounded FMA reach 1 there for both the forward's and the back
+    // projection's constants, so that an entry outside the footprint's
+    // support is exactly zero (the SIRT weights invert the row and column
+    // sums).  With a = 0 the term u multiplies is zero and nothing is needed.
+    float nh32 = (float)val[3];
+    double nh64 = val[3];
+    if (lo > 0.0) {
+        const float h1 = (float)val[1], i1 = (float)val[2], h2 = (float)val[7], i2 = (float)val[8];
+        for (int k = 0; k < 16 && (fmaf(h1, i1, nh32) < 1.0f || fmaf(h2, i2, nh32) < 1.0f); ++k)
+            nh32 = nextafterf(nh32, INFINITY);
+        for (int k = 0; k < 16 && (fma(val[1], val[2], nh64) < 1.0 || fma(val[7], val[8], nh64) < 1.0); ++k)
+            nh64 = nextafter(nh64, INFINITY);
+    }
 #pragma unroll
     for (int k = 0; k < kRayTables; ++k) {
-        if (a.f32[k]) a.f32[k][r] = (float)val[k];
-        if (a.f64[k]) a.f64[k][r] = val[k];
+        if (a.f32[k]) a.f32[k][r] = k == 3 ? nh32 : (float)val[k];
+        if (a.f64[k]) a.f64[k][r] = k == 3 ? nh64 : val[k];
     }
 }
 
