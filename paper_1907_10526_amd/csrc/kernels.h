@@ -19,7 +19,8 @@
 // with T the antiderivative of the trapezoid M_[a,b].  T is odd about 1/2 and
 // its positive half, times b, is
 //     Gb(y) = m - (a/2) u^2,   m = min(y, h+),   u = clamp((m - h-) / a, 0, 1)
-// (h+ = (a+b)/2, h- = (b-a)/2): a min, one clamped FMA, a square.  No
+// (h+ = (a+b)/2, h- = (b-a)/2); footprint_num takes the two terms of the
+// moving average together (a median, a clamped FMA and a square each).  No
 // truncated power is differenced, so there is no cancellation for near-zero
 // a (axis-aligned rays: the rounding of u is then multiplied by a/2) and
 // everything runs in FP32.  FP64 is kept for the per-view fan geometry and
@@ -211,7 +212,7 @@ struct RayWalk {
     size_t img_stride; // values between images of the copy
 };
 
-// Row stepper of walk_rows.  FP64 (the FP64 instantiation): X itself.
+// Row stepper of walk_block.  FP64 (the FP64 instantiation): X itself.
 // FP32: X + kFwdPad in 32.32 fixed point, re-anchored from the FP64 X at the
 // start of every block of kSumBlock rows (so its drift stays below
 // kSumBlock * 2^-33 pixel); one 64-bit integer add per row, the high word is
