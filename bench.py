@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "5f2ecdf5a73dedd6b44aeaac83f4b143eacbc6c20a6927157663b37199d7f648",
+    "sources_sha256": "7d2eca09807ac88270ee92ec1afed7342ee708defadf44eee5e2aa089e5c7fab",
     "bytes_per_launch": {"forward": 35995227, "back": 197737755},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
