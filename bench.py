@@ -94,7 +94,7 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
     p.add_argument("--serve-budget-gib", type=float, default=2.0,
                    help="device-memory budget of the serving loop")
-    p.add_argument("--serve-step-work", type=float, default=1.5e10,
+    p.add_argument("--serve-step-work", type=float, default=4e9,
                    help="matrix entries one serving step may evaluate (the oldest job always goes)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one device-to-device copy of this many MiB before timing, as a "

@@ -171,7 +171,7 @@ class Server:
     """
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
-                 step_work: float = 1.5e10, clock=None, keep_outputs: bool = False,
+                 step_work: float = 4e9, clock=None, keep_outputs: bool = False,
                  depth: int = 2):
         self.ex = executor
         self.budget = int(hbm_budget)
