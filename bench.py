@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "7d2eca09807ac88270ee92ec1afed7342ee708defadf44eee5e2aa089e5c7fab",
-    "bytes_per_launch": {"forward": 35995227, "back": 197737755},
+    "sources_sha256": "8667bf62d76c42082f3beaa9a33d620b6376f7725bfceb42c2c459f5161d46b1",
+    "bytes_per_launch": {"forward": 35994022, "back": 197722888},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",

@@ -14,12 +14,11 @@ hipError_t launch_fwd_t(const DevGeom &g, const Real *img, Real *work, Real *out
         Real *wr = work;
         Real *wc = work + (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
         const size_t total = (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
-        const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
-        hipLaunchKernelGGL(pad_rows_kernel<Real>, dim3(blocks), dim3(256), 0, stream, img, wr, g.nx,
-                           g.ny, nrows, NB);
-        dim3 tgrid((nrows + 31) / 32, (g.ny + 2 * kFwdPad + 31) / 32, NB);
-        hipLaunchKernelGGL(pad_cols_kernel<Real>, tgrid, dim3(32, 8), 0, stream, img, wc, g.nx,
-                           g.ny, nrows);
+        const unsigned rows_blocks = (unsigned)std::min<size_t>((total + 255) / 256, 4096);
+        const int ti = (nrows + 31) / 32, tp = (g.ny + 2 * kFwdPad + 31) / 32;
+        hipLaunchKernelGGL(pad_kernel<Real>, dim3(rows_blocks + (unsigned)(ti * tp * NB)),
+                           dim3(32, 8), 0, stream, img, wr, wc, g.nx, g.ny, nrows, NB,
+                           rows_blocks, ti, tp);
         rows = wr;
         cols = wc;
     }

@@ -165,23 +165,27 @@ __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real
     __syncthreads();
 }
 
+// Both padded copies of a batch in one launch of 32 x 8 blocks: the first
+// rows_blocks blocks stride over the row copies, each further block
+// transposes one 32 x 32 tile of one image's column copy (ti x tp tiles per
+// image).
 template <typename Real>
-__global__ __launch_bounds__(256) void pad_rows_kernel(const Real *__restrict__ img,
-                                                       Real *__restrict__ rows, int nx, int ny,
-                                                       int nrows, int nb) {
-    pad_rows_body(img, rows, nx, ny, nrows, nb, (size_t)blockIdx.x * blockDim.x + threadIdx.x,
-                  (size_t)gridDim.x * blockDim.x);
-}
-
-template <typename Real>
-__global__ __launch_bounds__(256) void pad_cols_kernel(const Real *__restrict__ img,
-                                                       Real *__restrict__ cols, int nx, int ny,
-                                                       int nrows) {
+__global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
+                                                  Real *__restrict__ rows, Real *__restrict__ cols,
+                                                  int nx, int ny, int nrows, int nb,
+                                                  unsigned rows_blocks, int ti, int tp) {
     __shared__ Real tile[32][33];
-    const int b = blockIdx.z;
+    const int tid = threadIdx.y * 32 + threadIdx.x;
+    if (blockIdx.x < rows_blocks) {
+        pad_rows_body(img, rows, nx, ny, nrows, nb, (size_t)blockIdx.x * 256 + tid,
+                      (size_t)rows_blocks * 256);
+        return;
+    }
+    const int t = (int)(blockIdx.x - rows_blocks);
+    const int b = t / (ti * tp), k = t % (ti * tp);
     const int w = ny + 2 * kFwdPad;
     pad_cols_tile(img + (size_t)b * nx * ny, cols + (size_t)b * nrows * w, nx, ny, nrows,
-                  blockIdx.x * 32, blockIdx.y * 32, tile);
+                  (k % ti) * 32, (k / ti) * 32, tile);
 }
 
 // ---------------------------------------------------------------------------
