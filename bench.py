@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0
 # for the kernel sources they were taken on: `traffic` is reported as null
 # once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "8667bf62d76c42082f3beaa9a33d620b6376f7725bfceb42c2c459f5161d46b1",
+    "sources_sha256": "4c79e8c61b40fa4e1a4d190520b14c03783d5e07420ef9f1139120a9d6f3c3f9",
     "bytes_per_launch": {"forward": 35994022, "back": 197722888},
     "profile": "profiles/cnsf_projection_pair_512x720x1024.md",
 }

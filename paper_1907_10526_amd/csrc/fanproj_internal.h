@@ -51,7 +51,7 @@ constexpr size_t kBackLdsLimit = 64 * 1024;
 // The back projection splits the views into groups (gridDim.z) until about
 // this many work-groups per compute unit are in flight.
 constexpr int kBackGroupsPerCu = 8;
-constexpr int kBackMaxGroups = 8;
+constexpr int kBackMaxGroups = 32;
 
 // Per-ray constants, [nv][nd] each, in the kernels' arithmetic type: FP32
 // roundings of FP64 values for the production kernels, the FP64 values
