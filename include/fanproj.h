@@ -40,6 +40,13 @@
  * threads and streams may then share it.  Kernel faults surface at the
  * caller's next synchronisation, or as FP_ERR_DEVICE from a later call.
  *
+ * Scratch: the launches' temporary buffers (padded image copies, view-group
+ * partial sums) come from per-device buffers the library keeps for the life
+ * of the process and reuses across calls, streams and threads; each reuse is
+ * ordered on the device after the buffer's previous use by an event, so
+ * calls do not wait on the host.  A buffer grows (after its last use has
+ * finished) when a call needs more than it holds.
+ *
  * Errors: no exception crosses this interface.  Every function returns an
  * fp_status; for a non-OK status fp_last_error() gives a message (per calling
  * thread).  Outputs are left untouched when arguments are rejected.
