@@ -25,6 +25,11 @@ constexpr int kBackPixPerThread = kBackTileW * kBackTileH / kBackThreads;
 // visits along a row or column are contiguous and need no bounds checks.
 constexpr int kFwdThreads = 256;
 constexpr int kFwdPad = 16;          // zero margin on each side of the cross axis
+// Row length of both padded copies: the longer image side plus the margins,
+// so that every ray sees one row stride and one clamp bound.
+__host__ __device__ constexpr int padded_width(int nx, int ny) {
+    return (nx > ny ? nx : ny) + 2 * kFwdPad;
+}
 constexpr int kFwdMaxUnrolled = 8;   // widest row window with an unrolled variant
 // Batch images processed per launch (the kernels are instantiated for
 // 1, 2, 4 and 8 images sharing one evaluation of every entry).

@@ -12,10 +12,11 @@ hipError_t launch_fwd_t(const DevGeom &g, const Real *img, Real *work, Real *out
     if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
         const int nrows = std::max(g.nx, g.ny);
         Real *wr = work;
-        Real *wc = work + (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
-        const size_t total = (size_t)NB * nrows * (g.nx + 2 * kFwdPad);
+        const int width = padded_width(g.nx, g.ny);
+        Real *wc = work + (size_t)NB * nrows * width;
+        const size_t total = (size_t)NB * nrows * width;
         const unsigned rows_blocks = (unsigned)std::min<size_t>((total + 255) / 256, 4096);
-        const int ti = (nrows + 31) / 32, tp = (g.ny + 2 * kFwdPad + 31) / 32;
+        const int ti = (nrows + 31) / 32, tp = (width + 31) / 32;
         hipLaunchKernelGGL(pad_kernel<Real>, dim3(rows_blocks + (unsigned)(ti * tp * NB)),
                            dim3(32, 8), 0, stream, img, wr, wc, g.nx, g.ny, nrows, NB,
                            rows_blocks, ti, tp);
@@ -45,7 +46,7 @@ hipError_t launch_fwd_nb(const DevGeom &g, int nb, const Real *img, Real *work, 
 template <typename Real>
 size_t forward_work_bytes(const DevGeom &g, int nb) {
     const size_t nrows = (size_t)std::max(g.nx, g.ny);
-    return (size_t)nb * sizeof(Real) * nrows * ((size_t)(g.nx + 2 * kFwdPad) + (g.ny + 2 * kFwdPad));
+    return (size_t)nb * sizeof(Real) * nrows * 2 * (size_t)padded_width(g.nx, g.ny);
 }
 
 template <typename Real>

@@ -121,17 +121,18 @@ constexpr int kSumBlock = 32;
 
 // ---------------------------------------------------------------------------
 // Padded image copies for the forward walk, each with NR = max(nx, ny) rows
-// (rows past the image are zero, so a wave whose rays march along different
-// axes can walk the union of their row ranges):
-//   row copy  [nb][NR][nx + 2 pad]: pixel (i, j) at j * (nx + 2 pad) + pad + i
-//   col copy  [nb][NR][ny + 2 pad]: pixel (i, j) at i * (ny + 2 pad) + pad + j
+// of W = NR + 2 pad values (rows and values past the image are zero, so a
+// wave whose rays march along different axes can walk the union of their row
+// ranges with one row stride and one clamp bound):
+//   row copy  [nb][NR][W]: pixel (i, j) at j * W + pad + i
+//   col copy  [nb][NR][W]: pixel (i, j) at i * W + pad + j
 // ---------------------------------------------------------------------------
 // Row copy of images [0, nb): work item e of the flattened copy.
 template <typename Real>
 __device__ __forceinline__ void pad_rows_body(const Real *__restrict__ img, Real *__restrict__ rows,
                                               int nx, int ny, int nrows, int nb, size_t first,
                                               size_t stride) {
-    const int w = nx + 2 * kFwdPad;
+    const int w = padded_width(nx, ny);
     const size_t per = (size_t)w * nrows;
     const size_t total = per * nb;
     for (size_t e = first; e < total; e += stride) {
@@ -148,7 +149,7 @@ template <typename Real>
 __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real *__restrict__ dst,
                                               int nx, int ny, int nrows, int i0, int p0,
                                               Real (&tile)[32][33]) {
-    const int w = ny + 2 * kFwdPad;
+    const int w = padded_width(nx, ny);
     // read: rows j = p - pad, columns i (coalesced along i)
     for (int k = threadIdx.y; k < 32; k += 8) {
         const int p = p0 + k, j = p - kFwdPad, i = i0 + (int)threadIdx.x;
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
     }
     const int t = (int)(blockIdx.x - rows_blocks);
     const int b = t / (ti * tp), k = t % (ti * tp);
-    const int w = ny + 2 * kFwdPad;
+    const int w = padded_width(nx, ny);
     pad_cols_tile(img + (size_t)b * nx * ny, cols + (size_t)b * nrows * w, nx, ny, nrows,
                   (k % ti) * 32, (k / ti) * 32, tile);
 }
@@ -209,6 +210,7 @@ struct RayWalk {
     float hqa, hqb;
     Trap<Real> trap;
     int nq;            // pixels along the cross axis
+    int width;         // length of a padded copy's rows (uniform)
     int nr;            // pixels along the march axis
     int r0;            // first row of the walk
     const Real *base;  // padded copy, cross index 0 of row 0 (image 0)
@@ -236,28 +238,26 @@ struct RowStepper {
 };
 template <>
 struct RowStepper<float> {
-    double X;              // FP64 X at the start of the block
-    unsigned lo, hi;       // X + kFwdPad in 32.32 fixed point (hi signed)
-    unsigned dlo, dhi;     // its step per row
+    double X;                // FP64 X at the start of the block
+    unsigned long long q;    // X + kFwdPad in 32.32 fixed point (two's complement)
+    unsigned long long dq;   // its step per row
     __device__ void start(double X0) { X = X0; }
     __device__ void anchor(double dX) {
         const double xb = X + kFwdPad, fl = floor(xb);
-        hi = (unsigned)(int)fl;
-        lo = (unsigned)((xb - fl) * 4294967296.0);
-        const long long d = (long long)rint(dX * 4294967296.0);   // |dX| <= 1
-        dlo = (unsigned)d;
-        dhi = (unsigned)(d >> 32);
+        q = (unsigned long long)((long long)fl * 4294967296LL) +
+            (unsigned)((xb - fl) * 4294967296.0);
+        dq = (unsigned long long)(long long)rint(dX * 4294967296.0);   // |dX| <= 1
     }
     // (a negative X + kFwdPad wraps to a large unsigned value and clamps to
     // p_max, a window in the zero margin on the far side)
     __device__ __forceinline__ void row(unsigned p_max, unsigned &p, float &frac) {
-        p = min(hi, p_max);
-        frac = (float)lo;   // the fraction in units of 2^-32
+        p = min((unsigned)(q >> 32), p_max);
+        frac = (float)(unsigned)q;   // the fraction in units of 2^-32
     }
+    // One 64-bit add (written out: the compiler's loop strength reduction
+    // otherwise splits the stepper into several induction variables).
     __device__ __forceinline__ void next(double) {
-        const unsigned l = lo + dlo;
-        hi += dhi + (l < lo ? 1u : 0u);
-        lo = l;
+        asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(q) : "v"(q), "v"(dq));
     }
 };
 
@@ -273,7 +273,7 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
     // the window start, clamped so that the window stays inside the padded
     // copy (a clamped window, and the unclamped one it replaces, lie in the
     // zero margin: its s' is then immaterial)
-    const unsigned p_max = (unsigned)(w.nq + 2 * kFwdPad - T);
+    const unsigned p_max = (unsigned)(w.width - T);
     // s' at the window start is zc (1 - hq - frac(X)); in fixed point frac
     // arrives in units of 2^-32
     const Real zfrac = kFixed ? -w.zcr * Real(2.3283064365386963e-10) : -w.zcr;
@@ -290,8 +290,7 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
         hcp += w.dhr;
         Real cv[NB][T];
         if constexpr (kLoad) {
-            const Real *pp = reinterpret_cast<const Real *>(
-                reinterpret_cast<const char *>(rowp) + (p * (unsigned)sizeof(Real)));
+            const Real *pp = rowp + p;
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -473,7 +472,8 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     w.zcr = (Real)zc;
     w.nq = nq;
     w.nr = nr;
-    w.row_stride = (size_t)nq + 2 * kFwdPad;
+    w.width = padded_width(G.nx, G.ny);
+    w.row_stride = (size_t)w.width;
     w.img_stride = w.row_stride * (size_t)max(G.nx, G.ny);
     w.base = (by_rows ? rows : cols) + kFwdPad;
 

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void pad_multi_kernel(const MultiArgs A) {
     const int tid = threadIdx.y * 32 + threadIdx.x;
     pad_rows_body<float>(J.image, J.rows, nx, ny, nrows, 1, (size_t)blockIdx.x * 256 + tid,
                          (size_t)gridDim.x * 256);
-    const int ti = (nrows + 31) / 32, tp = (ny + 2 * kFwdPad + 31) / 32;
+    const int ti = (nrows + 31) / 32, tp = (padded_width(nx, ny) + 31) / 32;
     for (int t = blockIdx.x; t < ti * tp; t += gridDim.x)
         pad_cols_tile<float>(J.image, J.cols, nx, ny, nrows, (t % ti) * 32, (t / ti) * 32, tile);
 }
