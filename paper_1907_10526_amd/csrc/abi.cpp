@@ -470,8 +470,7 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
             MultiJob &M = args.job[k];
             M.g = g->dev;
             const int nrows = std::max(g->nx, g->ny);
-            M.rows = reinterpret_cast<float *>(base + off);
-            M.cols = M.rows + (size_t)nrows * padded_width(g->nx, g->ny);
+            M.copies = reinterpret_cast<float *>(base + off);
             off += (forward_work_bytes<float>(g->dev, 1) + 255) / 256 * 256;
             M.partial = reinterpret_cast<float *>(base + off);
             off += (back_work_bytes<float>(g->dev, 1) + 255) / 256 * 256;

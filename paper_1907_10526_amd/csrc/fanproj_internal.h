@@ -191,7 +191,7 @@ constexpr int kMaxJobsPerLaunch = 12;
 struct MultiJob {
     DevGeom g;
     const float *image;     // [ny][nx] iterate, read by the forward phase
-    float *rows, *cols;     // padded copies (scratch)
+    float *copies;          // the interleaved padded copies (scratch)
     float *image_out;       // the iterate, updated by the back phase
     const float *y_meas;    // [nv][nd]
     float *work;            // [nv][nd] residual R .* (y - A x)
@@ -206,7 +206,7 @@ struct MultiArgs {
     MultiJob job[kMaxJobsPerLaunch];
 };
 static_assert(sizeof(MultiArgs) <= 4000, "kernel arguments must stay under 4 KB");
-// Launch the three phases for args.job[0 .. n) (multi.hip); rows/cols/
+// Launch the three phases for args.job[0 .. n) (multi.hip); copies/
 // partial/fwd_begin must be filled in (partial: back_work_bytes<float>(g, 1)
 // bytes).
 hipError_t launch_sirt_multi(const MultiArgs &args, hipStream_t stream);

@@ -8,24 +8,21 @@ namespace {
 template <typename Real, int NB, FwdMode MODE>
 hipError_t launch_fwd_t(const DevGeom &g, const Real *img, Real *work, Real *out, int *counts,
                         const Real *y_meas, const Real *row_w, hipStream_t stream) {
-    const Real *rows = nullptr, *cols = nullptr;
+    const Real *copies = nullptr;
     if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
         const int nrows = std::max(g.nx, g.ny);
-        Real *wr = work;
         const int width = padded_width(g.nx, g.ny);
-        Real *wc = work + (size_t)NB * nrows * width;
         const size_t total = (size_t)NB * nrows * width;
         const unsigned rows_blocks = (unsigned)std::min<size_t>((total + 255) / 256, 4096);
         const int ti = (nrows + 31) / 32, tp = (width + 31) / 32;
         hipLaunchKernelGGL(pad_kernel<Real>, dim3(rows_blocks + (unsigned)(ti * tp * NB)),
-                           dim3(32, 8), 0, stream, img, wr, wc, g.nx, g.ny, nrows, NB,
+                           dim3(32, 8), 0, stream, img, work, g.nx, g.ny, nrows, NB,
                            rows_blocks, ti, tp);
-        rows = wr;
-        cols = wc;
+        copies = work;
     }
     dim3 grid((g.nd + kFwdThreads - 1) / kFwdThreads, g.nv);
     hipLaunchKernelGGL((forward_kernel<Real, NB, MODE>), grid, dim3(kFwdThreads), 0, stream, g,
-                       rows, cols, out, counts, y_meas, row_w);
+                       copies, out, counts, y_meas, row_w);
     return hipGetLastError();
 }
 

@@ -120,31 +120,34 @@ __device__ __forceinline__ int wave_min(int x) {
 constexpr int kSumBlock = 32;
 
 // ---------------------------------------------------------------------------
-// Padded image copies for the forward walk, each with NR = max(nx, ny) rows
-// of W = NR + 2 pad values (rows and values past the image are zero, so a
-// wave whose rays march along different axes can walk the union of their row
-// ranges with one row stride and one clamp bound):
-//   row copy  [nb][NR][W]: pixel (i, j) at j * W + pad + i
-//   col copy  [nb][NR][W]: pixel (i, j) at i * W + pad + j
+// Padded image copies for the forward walk, row-major and transposed, each
+// with NR = max(nx, ny) rows of W = NR + 2 pad values (rows and values past
+// the image are zero, so a wave whose rays march along different axes can
+// walk the union of their row ranges with one clamp bound), interleaved row
+// by row: copies [nb][NR][2][W], so that row r of either copy is at one
+// address common to the wave plus a small per-lane offset (0 or W):
+//   row copy  (slot 0): pixel (i, j) at (j * 2 + 0) * W + pad + i
+//   col copy  (slot 1): pixel (i, j) at (i * 2 + 1) * W + pad + j
 // ---------------------------------------------------------------------------
-// Row copy of images [0, nb): work item e of the flattened copy.
+// Row copy (slot 0) of images [0, nb): work item e of the flattened copy.
 template <typename Real>
-__device__ __forceinline__ void pad_rows_body(const Real *__restrict__ img, Real *__restrict__ rows,
-                                              int nx, int ny, int nrows, int nb, size_t first,
-                                              size_t stride) {
+__device__ __forceinline__ void pad_rows_body(const Real *__restrict__ img,
+                                              Real *__restrict__ copies, int nx, int ny,
+                                              int nrows, int nb, size_t first, size_t stride) {
     const int w = padded_width(nx, ny);
-    const size_t per = (size_t)w * nrows;
-    const size_t total = per * nb;
+    const size_t total = (size_t)w * nrows * nb;
     for (size_t e = first; e < total; e += stride) {
-        const size_t b = e / per, r = e % per;
-        const int j = (int)(r / w), i = (int)(r % w) - kFwdPad;
-        rows[e] = (i >= 0 && i < nx && j < ny) ? img[b * (size_t)nx * ny + (size_t)j * nx + i]
-                                               : Real(0);
+        const size_t row = e / w;    // b * nrows + j
+        const int j = (int)(row % nrows), i = (int)(e % w) - kFwdPad;
+        const size_t b = row / nrows;
+        copies[row * 2 * w + e % w] =
+            (i >= 0 && i < nx && j < ny) ? img[b * (size_t)nx * ny + (size_t)j * nx + i] : Real(0);
     }
 }
 
 // Tiled transpose through LDS: block (32, 8) handles a 32 x 32 tile of the
-// column copy (32 copy rows i from i0, 32 padded positions p from p0).
+// column copy (32 copy rows i from i0, 32 padded positions p from p0); dst is
+// the image's column copy (slot 1 of its first row), rows 2 W apart.
 template <typename Real>
 __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real *__restrict__ dst,
                                               int nx, int ny, int nrows, int i0, int p0,
@@ -161,7 +164,7 @@ __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real
     // write: column copy row i, positions p (coalesced along p)
     for (int k = threadIdx.y; k < 32; k += 8) {
         const int i = i0 + k, p = p0 + (int)threadIdx.x;
-        if (i < nrows && p < w) dst[(size_t)i * w + p] = tile[threadIdx.x][k];
+        if (i < nrows && p < w) dst[(size_t)i * 2 * w + p] = tile[threadIdx.x][k];
     }
     __syncthreads();
 }
@@ -172,21 +175,21 @@ __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real
 // image).
 template <typename Real>
 __global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
-                                                  Real *__restrict__ rows, Real *__restrict__ cols,
-                                                  int nx, int ny, int nrows, int nb,
-                                                  unsigned rows_blocks, int ti, int tp) {
+                                                  Real *__restrict__ copies, int nx, int ny,
+                                                  int nrows, int nb, unsigned rows_blocks, int ti,
+                                                  int tp) {
     __shared__ Real tile[32][33];
     const int tid = threadIdx.y * 32 + threadIdx.x;
     if (blockIdx.x < rows_blocks) {
-        pad_rows_body(img, rows, nx, ny, nrows, nb, (size_t)blockIdx.x * 256 + tid,
+        pad_rows_body(img, copies, nx, ny, nrows, nb, (size_t)blockIdx.x * 256 + tid,
                       (size_t)rows_blocks * 256);
         return;
     }
     const int t = (int)(blockIdx.x - rows_blocks);
     const int b = t / (ti * tp), k = t % (ti * tp);
     const int w = padded_width(nx, ny);
-    pad_cols_tile(img + (size_t)b * nx * ny, cols + (size_t)b * nrows * w, nx, ny, nrows,
-                  (k % ti) * 32, (k / ti) * 32, tile);
+    pad_cols_tile(img + (size_t)b * nx * ny, copies + ((size_t)b * nrows * 2 + 1) * w, nx, ny,
+                  nrows, (k % ti) * 32, (k / ti) * 32, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -211,11 +214,12 @@ struct RayWalk {
     Trap<Real> trap;
     int nq;            // pixels along the cross axis
     int width;         // length of a padded copy's rows (uniform)
+    int lane_off;      // offset of this ray's copy within a row pair: 0 or width
     int nr;            // pixels along the march axis
     int r0;            // first row of the walk
-    const Real *base;  // padded copy, cross index 0 of row 0 (image 0)
-    size_t row_stride; // values between rows of the copy
-    size_t img_stride; // values between images of the copy
+    const Real *base;  // the interleaved copies (image 0, row 0), uniform
+    size_t row_stride; // values between rows of a copy (2 width)
+    size_t img_stride; // values between images
 };
 
 // Row stepper of walk_block.  FP64 (the FP64 instantiation): X itself.
@@ -277,7 +281,9 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
     // s' at the window start is zc (1 - hq - frac(X)); in fixed point frac
     // arrives in units of 2^-32
     const Real zfrac = kFixed ? -w.zcr * Real(2.3283064365386963e-10) : -w.zcr;
-    const Real *rowp = w.base - kFwdPad + (size_t)rb * w.row_stride;
+    // row r of both copies starts at one address common to the wave; the
+    // lane's window is a small byte offset from it
+    const Real *rowp = w.base + (size_t)rb * w.row_stride;
     RowStepper<Real> X;
     X.start(Xb);
     if constexpr (kFixed) X.anchor(w.dX);
@@ -290,7 +296,9 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
         hcp += w.dhr;
         Real cv[NB][T];
         if constexpr (kLoad) {
-            const Real *pp = rowp + p;
+            const Real *pp = reinterpret_cast<const Real *>(
+                reinterpret_cast<const char *>(rowp) +
+                (unsigned)(w.lane_off + (int)p) * (unsigned)sizeof(Real));
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -324,7 +332,7 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
 template <typename Real, int NB, FwdMode MODE>
 __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp_top, Real hcp,
                                 int rb, int re, Real (&blk)[NB], int &nonzero) {
-    const Real *rowp = w.base - kFwdPad + (size_t)rb * w.row_stride;
+    const Real *rowp = w.base + w.lane_off + (size_t)rb * w.row_stride;
     for (int r = rb; r <= re; ++r, rowp += w.row_stride, X += w.dX, hcp += w.dhr) {
         const double fl = floor(X);
         const int q_lo = (int)fl;
@@ -396,8 +404,8 @@ __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (
 // m_block * kFwdThreads.
 template <typename Real, int NB, FwdMode MODE>
 __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_block,
-                                              const Real *__restrict__ rows,
-                                              const Real *__restrict__ cols, Real *__restrict__ out,
+                                              const Real *__restrict__ copies,
+                                              Real *__restrict__ out,
                                               int *__restrict__ counts,
                                               const Real *__restrict__ y_meas,
                                               const Real *__restrict__ row_w) {
@@ -473,9 +481,10 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     w.nq = nq;
     w.nr = nr;
     w.width = padded_width(G.nx, G.ny);
-    w.row_stride = (size_t)w.width;
+    w.row_stride = 2 * (size_t)w.width;
     w.img_stride = w.row_stride * (size_t)max(G.nx, G.ny);
-    w.base = (by_rows ? rows : cols) + kFwdPad;
+    w.base = copies;
+    w.lane_off = by_rows ? 0 : w.width;
 
     // Support |s'| < hab + hc, with hc bounded by its value at the far side
     // of the disk containing the image.
@@ -548,10 +557,10 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 
 template <typename Real, int NB, FwdMode MODE>
 __global__ __launch_bounds__(kFwdThreads, min_waves(NB, sizeof(Real))) void forward_kernel(
-    DevGeom G, const Real *__restrict__ rows, const Real *__restrict__ cols,
+    DevGeom G, const Real *__restrict__ copies,
     Real *__restrict__ out, int *__restrict__ counts, const Real *__restrict__ y_meas,
     const Real *__restrict__ row_w) {
-    forward_block<Real, NB, MODE>(G, blockIdx.y, blockIdx.x, rows, cols, out, counts, y_meas,
+    forward_block<Real, NB, MODE>(G, blockIdx.y, blockIdx.x, copies, out, counts, y_meas,
                                   row_w);
 }
 

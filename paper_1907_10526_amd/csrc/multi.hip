@@ -24,11 +24,13 @@ __global__ __launch_bounds__(256) void pad_multi_kernel(const MultiArgs A) {
     const MultiJob &J = A.job[blockIdx.y];
     const int nx = J.g.nx, ny = J.g.ny, nrows = max(nx, ny);
     const int tid = threadIdx.y * 32 + threadIdx.x;
-    pad_rows_body<float>(J.image, J.rows, nx, ny, nrows, 1, (size_t)blockIdx.x * 256 + tid,
+    pad_rows_body<float>(J.image, J.copies, nx, ny, nrows, 1, (size_t)blockIdx.x * 256 + tid,
                          (size_t)gridDim.x * 256);
-    const int ti = (nrows + 31) / 32, tp = (padded_width(nx, ny) + 31) / 32;
+    const int w = padded_width(nx, ny);
+    const int ti = (nrows + 31) / 32, tp = (w + 31) / 32;
     for (int t = blockIdx.x; t < ti * tp; t += gridDim.x)
-        pad_cols_tile<float>(J.image, J.cols, nx, ny, nrows, (t % ti) * 32, (t / ti) * 32, tile);
+        pad_cols_tile<float>(J.image, J.copies + w, nx, ny, nrows, (t % ti) * 32, (t / ti) * 32,
+                             tile);
 }
 
 __global__ __launch_bounds__(kFwdThreads, 8) void forward_multi_kernel(const MultiArgs A) {
@@ -36,7 +38,7 @@ __global__ __launch_bounds__(kFwdThreads, 8) void forward_multi_kernel(const Mul
     const MultiJob &J = A.job[j];
     const unsigned local = blockIdx.x - J.fwd_begin;
     const unsigned bx = (J.g.nd + kFwdThreads - 1) / kFwdThreads;
-    forward_block<float, 1, FwdMode::kSirtResidual>(J.g, local / bx, local % bx, J.rows, J.cols,
+    forward_block<float, 1, FwdMode::kSirtResidual>(J.g, local / bx, local % bx, J.copies,
                                                    J.work, nullptr, J.y_meas, J.row_w);
 }
 
