@@ -88,8 +88,11 @@ struct RayTables {
     __host__ __device__ const Real *bhab() const { return at(7); }   // hab R_m
     __host__ __device__ const Real *bia() const { return at(8); }    // ia / R_m
     __host__ __device__ const Real *bha() const { return at(9); }    // ha R_m
+    // wb / bgh: the back projection divides an entry's footprint by R_m L
+    // alone and folds the blur constant into the staged weight
+    __host__ __device__ const Real *bwg() const { return at(10); }
 };
-constexpr int kRayTables = 10;
+constexpr int kRayTables = 11;
 
 // Read-only description of a geometry as the kernels see it.  All pointers
 // are device pointers owned by fp_geometry.

@@ -594,6 +594,8 @@ struct Pair<double> {
 // with an immediate offset from one base address: (blur, hab), (1/a,
 // -(b-a)/(2a)), (a/2, weight of image 0), then the other images' weights two
 // by two (an odd last one paired with zero); all scaled as the back tables.
+// A weight is the sinogram value times the normalisation over the blur
+// constant (table bwg).
 constexpr int back_weight_pairs(int nb) { return nb / 2; }
 static_assert(5 == kBackRayParams, "five per-ray parameters");
 template <typename Real, int NB, int CAP>
@@ -636,7 +638,7 @@ __device__ __forceinline__ void back_prefetch(const DevGeom &G, const RayTables<
             st.ia[k] = at(tab.bia());
             st.nhbia[k] = at(tab.nhbia());
             st.ha[k] = at(tab.bha());
-            const Real wb = at(tab.wb());
+            const Real wb = at(tab.bwg());
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const Real w = (MODE == BackMode::kOnes ? Real(1) : at(sino + b * nrays)) * wb;
@@ -706,12 +708,15 @@ __device__ __forceinline__ void back_window(const BackLds<Real, NB, CAP> &l, int
     const auto *gh_hab = l.gh_hab + w0;
     const auto *ia_nhbia = l.ia_nhbia + w0;
     const auto *ha_w0 = l.ha_w0 + w0;
-    // num = s' R_m and ln = R_m L at cell t; the staged constants carry R_m
+    // num = s' R_m and ln = R_m L at cell t; the staged constants carry R_m.
+    // The entry is footprint / (ln g) times the weight; the staged weights
+    // are already divided by the blur constant g, so only ln is inverted
+    // (hc R_m = ln g then appears only inside the footprint's FMAs).
     auto entry = [&](int t, Real num, Real ln) {
         const auto a = gh_hab[t], b = ia_nhbia[t], c = ha_w0[t];
         const Real hcR = ln * a.x;
         const Trap<Real> p{a.y, b.x, b.y, c.x};
-        const Real e = footprint_num(num, hcR, p) * fast_rcp(hcR);
+        const Real e = footprint_num(num, hcR, p) * fast_rcp(ln);
         back_accumulate<Real, NB, CAP>(l, w0 + t, e, c.y, part);
     };
     if constexpr (UNROLLED) {
@@ -743,11 +748,12 @@ __device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l,
     const auto *gh_hab = l.gh_hab + w0;
     const auto *ia_nhbia = l.ia_nhbia + w0;
     const auto *ha_w0 = l.ha_w0 + w0;
+    // (staged weights divided by the blur constant, as in back_window)
     auto entry = [&](int t, Real sp, Real L) {
         const auto a = gh_hab[t], b = ia_nhbia[t], c = ha_w0[t];
         const Real hc = L * a.x;
         const Trap<Real> p{a.y, b.x, b.y, c.x};
-        const Real e = footprint_num(sp, hc, p) * fast_rcp(hc);
+        const Real e = footprint_num(sp, hc, p) * fast_rcp(L);
         back_accumulate<Real, NB, CAP>(l, w0 + t, e, c.y, part);
     };
     const double2 *cells = G.arc_cells + m_first + kBackPad;

@@ -74,6 +74,7 @@ __global__ __launch_bounds__(256) void ray_tables_kernel(const double2 *__restri
         0.5 * (lo + hi) * Rs,          // bhab
         1.0 / (a_safe * Rs),           // bia
         0.5 * lo * Rs,                 // bha
+        delta * delta / (2.0 * hi) / (f.ghr * Rs),   // bwg
     };
     // The kernels form u = clamp(m / a + nhbia) with m <= hab, which is 1 in
     // exact arithmetic at m = hab: nhbia is raised by the few ulps that make

@@ -88,12 +88,12 @@ def job_iteration_work(spec: JobSpec) -> float:
 
 def job_device_bytes(spec: JobSpec) -> int:
     """Upper estimate of the device memory a job holds while admitted: the
-    FP32 per-ray tables (10 per ray), per-view and per-tile tables, the SIRT
+    FP32 per-ray tables (11 per ray), per-view and per-tile tables, the SIRT
     weights, iterate, sinogram, residual and the padded image copies."""
     rays = spec.n_views * spec.n_det
     pix = spec.n * spec.n
     tiles = math.ceil(spec.n / 16) * math.ceil(spec.n / 32)
-    tables = 4 * 10 * rays + 16 * spec.n_views + 16 * spec.n_views * tiles
+    tables = 4 * 11 * rays + 16 * spec.n_views + 16 * spec.n_views * tiles
     weights = 4 * (rays + pix)
     buffers = 4 * (pix + 2 * rays)
     pad = 4 * spec.n * 2 * (spec.n + 32)
