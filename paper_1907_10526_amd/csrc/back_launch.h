@@ -22,7 +22,7 @@ hipError_t launch_back_t(const DevGeom &g, const Real *sino, Real *img, Real *pa
         return hipErrorInvalidValue;  // excluded by back_max_batch
     } else {
         const int groups = partial ? g.back_groups : 1;
-        dim3 grid(g.tiles_x, g.tiles_y, groups);
+        dim3 grid((unsigned)(g.tiles_x * g.tiles_y * groups));
         hipLaunchKernelGGL((back_kernel<Real, NB, CAP, MODE, BEAM>), grid, dim3(kBackThreads), 0,
                            stream, g, sino, img, partial, col_w, relaxation);
         if (groups > 1) {

@@ -56,6 +56,9 @@ constexpr size_t kBackLdsLimit = 64 * 1024;
 // The back projection splits the views into groups (gridDim.z) until about
 // this many work-groups per compute unit are in flight.
 constexpr int kBackGroupsPerCu = 8;
+// Accelerator dies (XCDs) of the part, each with its own L2; the hardware
+// hands out work-groups to them round-robin in linear work-group order.
+constexpr int kXcds = 8;
 constexpr int kBackMaxGroups = 32;
 
 // Per-ray constants, [nv][nd] each, in the kernels' arithmetic type: FP32
