@@ -163,6 +163,38 @@ def test_full_size_sampled(oracle_mod, fp, torch_cuda, name, nray, npix):
     assert err <= TOL
 
 
+def test_ragged_single_group_sampled(oracle_mod, fp, torch_cuda):
+    """1040 x 1030 pixels: 65 x 33 = 2145 back-projection tiles, so one view
+    group and a tile count that is not a multiple of the XCD count (the
+    work-group order then gives the XCDs bands of 269 and 268 tiles); ragged
+    tiles on two edges.  Sampled against the oracle, corners and tile edges
+    included."""
+    torch = torch_cuda
+    nx, ny, nv, nd = 1040, 1030, 30, 2200
+    angles = 2.0 * np.pi * np.arange(nv) / nv + 0.1
+    kw = dict(nx=nx, ny=ny, pixel=1.0, dsc=1600.0, dsd=2400.0, angles=angles, n_det=nd,
+              det_width=1.0)
+    og, gg = _pair(oracle_mod, fp, **kw)   # 8 work-groups per CU fill the chip: one group
+    img = phantoms.uniform((ny, nx), 21, 0.0, 1.0)
+    y = gg.forward(_to_gpu(torch, img)).cpu().numpy()
+    rng = np.random.default_rng(31)
+    rays = _sample(rng, 16, nv, nd) + [(v, nd // 2 + int(rng.integers(-30, 30))) for v in (0, 7, 19)]
+    got = np.array([y[v, m] for v, m in rays])
+    ref = np.array([og.forward_ray(img.astype(np.float64), v, m) for v, m in rays])
+    err = rel_l2(got, ref)
+    print(f"ragged single-group forward sampled rel-L2 {err:.3e}", flush=True)
+    assert err <= TOL
+    sino = phantoms.uniform((nv, nd), 22, 0.0, 1.0)
+    z = gg.back(_to_gpu(torch, sino)).cpu().numpy()
+    pix = _sample(rng, 30, nx, ny) + [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1),
+                                       (15, 31), (16, 32), (1039, 1023), (1024, 1024)]
+    got = np.array([z[j, i] for i, j in pix])
+    ref = np.array([og.back_pixel(sino.astype(np.float64), i, j) for i, j in pix])
+    err = rel_l2(got, ref)
+    print(f"ragged single-group back sampled rel-L2 {err:.3e}", flush=True)
+    assert err <= TOL
+
+
 def test_medium_disk_closed_form(fp, torch_cuda):
     """A uniform disk of radius 200 px projects to the bin average of
     2 sqrt(r^2 - d^2); the GPU result is within the pixelisation error."""
