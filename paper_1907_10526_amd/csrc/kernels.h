@@ -794,8 +794,14 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
     const int v_end = (int)(((long)G.nv * (group + 1)) / groups);
     constexpr int P = kBackPixPerThread;
     constexpr int kRowStep = kBackThreads / kBackTileW;
-    const int i = tx * kBackTileW + (int)(threadIdx.x % kBackTileW);
-    const int j0 = ty * kBackTileH + (int)(threadIdx.x / kBackTileW);
+    // A wave covers 16 columns x 4 rows of the tile, and each quarter-wave
+    // (16 lanes, served together by the LDS) a 4 x 4 block of them, whose
+    // windows lie within a few cells of each other: fewer LDS bank conflicts
+    // than a 16 x 1 row, whose windows spread over up to ~24 cells.
+    static_assert(kBackTileW == 16 && kBackThreads == 256, "lane -> pixel map");
+    const unsigned t = threadIdx.x;
+    const int i = tx * kBackTileW + (int)((t & 3u) | (((t >> 4) & 3u) << 2));
+    const int j0 = ty * kBackTileH + (int)(((t >> 2) & 3u) | ((t >> 6) << 2));
     bool valid[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) valid[p] = i < G.nx && j0 + p * kRowStep < G.ny;
