@@ -163,18 +163,22 @@ def test_full_size_sampled(oracle_mod, fp, torch_cuda, name, nray, npix):
     assert err <= TOL
 
 
-def test_ragged_single_group_sampled(oracle_mod, fp, torch_cuda):
+@pytest.mark.parametrize("beam", ["flat", "arc", "parallel"])
+def test_ragged_single_group_sampled(oracle_mod, fp, torch_cuda, beam):
     """1040 x 1030 pixels: 65 x 33 = 2145 back-projection tiles, so one view
     group and a tile count that is not a multiple of the XCD count (the
     work-group order then gives the XCDs bands of 269 and 268 tiles); ragged
     tiles on two edges.  Sampled against the oracle, corners and tile edges
     included."""
     torch = torch_cuda
-    nx, ny, nv, nd = 1040, 1030, 30, 2200
+    nx, ny, nv = 1040, 1030, 30
+    nd = 1500 if beam == "parallel" else 2200
     angles = 2.0 * np.pi * np.arange(nv) / nv + 0.1
     kw = dict(nx=nx, ny=ny, pixel=1.0, dsc=1600.0, dsd=2400.0, angles=angles, n_det=nd,
               det_width=1.0)
-    og, gg = _pair(oracle_mod, fp, **kw)   # 8 work-groups per CU fill the chip: one group
+    mode = {"flat": 0, "parallel": 1, "arc": 2}[beam]   # oracle modes
+    og = oracle_mod.Geometry(**kw, mode=mode)
+    gg = fp.Geometry(**kw, beam=beam)   # 8 work-groups per CU fill the chip: one group
     img = phantoms.uniform((ny, nx), 21, 0.0, 1.0)
     y = gg.forward(_to_gpu(torch, img)).cpu().numpy()
     rng = np.random.default_rng(31)
@@ -182,7 +186,7 @@ def test_ragged_single_group_sampled(oracle_mod, fp, torch_cuda):
     got = np.array([y[v, m] for v, m in rays])
     ref = np.array([og.forward_ray(img.astype(np.float64), v, m) for v, m in rays])
     err = rel_l2(got, ref)
-    print(f"ragged single-group forward sampled rel-L2 {err:.3e}", flush=True)
+    print(f"{beam} ragged single-group forward sampled rel-L2 {err:.3e}", flush=True)
     assert err <= TOL
     sino = phantoms.uniform((nv, nd), 22, 0.0, 1.0)
     z = gg.back(_to_gpu(torch, sino)).cpu().numpy()
@@ -191,7 +195,7 @@ def test_ragged_single_group_sampled(oracle_mod, fp, torch_cuda):
     got = np.array([z[j, i] for i, j in pix])
     ref = np.array([og.back_pixel(sino.astype(np.float64), i, j) for i, j in pix])
     err = rel_l2(got, ref)
-    print(f"ragged single-group back sampled rel-L2 {err:.3e}", flush=True)
+    print(f"{beam} ragged single-group back sampled rel-L2 {err:.3e}", flush=True)
     assert err <= TOL
 
 
