@@ -40,7 +40,7 @@
 // sinogram values of the cells its tile can touch in LDS, then every thread
 // sums its pixels' entries from LDS.  Each pixel is written once.
 //
-// Both kernels sum in two levels (over blocks of 32 rows / views, and over
+// Both kernels sum in two levels (over blocks of 64 rows / 32 views, and over
 // blocks) to keep the rounding of 10^3 - 10^4 FP32 terms well under 1e-6
 // relative.  Every kernel is instantiated for Real = float (the production
 // path) and Real = double (the same arithmetic in FP64 with FP64 tables, for
@@ -117,7 +117,8 @@ __device__ __forceinline__ int wave_min(int x) {
     return __builtin_amdgcn_readfirstlane(x);
 }
 
-constexpr int kSumBlock = 32;
+constexpr int kSumBlock = 32;        // views per partial sum of the back projection
+constexpr int kFwdBlockRows = 64;    // rows per block of the forward walk
 
 // ---------------------------------------------------------------------------
 // Padded image copies for the forward walk, row-major and transposed, each
@@ -224,8 +225,8 @@ struct RayWalk {
 
 // Row stepper of walk_block.  FP64 (the FP64 instantiation): X itself.
 // FP32: X + kFwdPad in 32.32 fixed point, re-anchored from the FP64 X at the
-// start of every block of kSumBlock rows (so its drift stays below
-// kSumBlock * 2^-33 pixel); one 64-bit integer add per row, the high word is
+// start of every block of kFwdBlockRows rows (so its drift stays below
+// kFwdBlockRows * 2^-33 pixel); one 64-bit integer add per row, the high word is
 // the padded cross index of the window start and the low word its fraction.
 template <typename Real>
 struct RowStepper {
@@ -359,15 +360,15 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
     }
 }
 
-// The walk over rows r0 .. r1 in blocks of kSumBlock rows.  Each block's
+// The walk over rows r0 .. r1 in blocks of kFwdBlockRows rows.  Each block's
 // window width is the wave's largest need over the block: the blur grows
 // with depth along the ray, so blocks on the source side take narrower
 // windows than the ray's deepest row would.
 template <typename Real, int NB, FwdMode MODE>
 __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (&acc)[NB],
                                           int &nonzero) {
-    for (int rb = w.r0; rb <= r1; rb += kSumBlock) {
-        const int re = min(rb + kSumBlock - 1, r1);
+    for (int rb = w.r0; rb <= r1; rb += kFwdBlockRows) {
+        const int re = min(rb + kFwdBlockRows - 1, r1);
         // the block's half span (a lane whose ray misses the block's rows
         // reads only the zero margin, whatever its window)
         const float ha = fmaf((float)(rb - w.r0), w.hqb, w.hqa);
