@@ -219,8 +219,13 @@ __global__ __launch_bounds__(256) void tile_table_kernel(const double2 *__restri
     // the first cell past c_k - H, and every non-zero cell lies past it.
     const float wc = (float)(-H / step - rel + 1.0);
     out[t] = make_int4(M0, cnt, T, __float_as_int(wc));
-    atomicMax(&maxima[0], cnt);
-    atomicMax(&maxima[1], T);
+    // (the maxima only grow, so a value no larger than one already read needs
+    // no atomic: most threads skip it instead of all contending for two
+    // addresses)
+    if (cnt > __hip_atomic_load(&maxima[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&maxima[0], cnt);
+    if (T > __hip_atomic_load(&maxima[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&maxima[1], T);
 }
 
 __global__ __launch_bounds__(256) void arc_cells_kernel(int nd, double pitch, double dsd,
