@@ -28,8 +28,8 @@ FLOPS_PER_ENTRY = 48
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed / dual issue) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
 # The same without packed FP32 instructions (one FP32 FMA per lane per cycle),
-# which this build keeps out of the generated code: the ceiling of the code
-# that runs.
+# which the library's build keeps out of the generated code: the ceiling of
+# the code that runs.
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
@@ -193,7 +193,7 @@ def serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the projector is not sharded "
+        print(json.dumps({"error": "bench.py measures one GPU: the projector is not sharded "
                                    "across GPUs (use --gpus 1)"}))
         sys.exit(2)
 

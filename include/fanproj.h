@@ -67,7 +67,7 @@ typedef enum {
                                  geometry with a pixel at or behind the source */
     FP_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed                    */
     FP_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed            */
-    FP_ERR_UNSUPPORTED = 4    /* valid but beyond this build's limits          */
+    FP_ERR_UNSUPPORTED = 4    /* valid but beyond the library's limits         */
 } fp_status;
 
 typedef struct fp_geometry fp_geometry;   /* opaque */
