@@ -72,6 +72,10 @@ def _lib():
         d.oracle_entry_terms.restype = None
         d.oracle_forward.argtypes = [P, dp, dp, ctypes.c_int]
         d.oracle_back.argtypes = [P, dp, dp, ctypes.c_int]
+        d.oracle_forward_cached.argtypes = [P, dp, dp]
+        d.oracle_forward_cached.restype = ctypes.c_int
+        d.oracle_back_cached.argtypes = [P, dp, dp]
+        d.oracle_back_cached.restype = ctypes.c_int
         d.oracle_forward_ray.argtypes = [P, dp, ctypes.c_int, ctypes.c_int]
         d.oracle_forward_ray.restype = ctypes.c_double
         d.oracle_back_pixel.argtypes = [P, dp, ctypes.c_int, ctypes.c_int]
@@ -153,16 +157,27 @@ class Geometry:
         return tuple(o.value for o in out)
 
     # -- operators --------------------------------------------------------
-    def forward(self, img, dense=False) -> np.ndarray:
+    def forward(self, img, dense=False, cached=False) -> np.ndarray:
+        """A c.  dense: every (ray, pixel) pair; cached: the same pruned sums
+        with the ray frames computed once (bitwise equal to the default)."""
         img = np.ascontiguousarray(img, dtype=np.float64).reshape(self.ny, self.nx)
         out = np.empty((self.n_views, self.n_det), dtype=np.float64)
-        _lib().oracle_forward(self._p, _dptr(img), _dptr(out), int(bool(dense)))
+        if cached and not dense:
+            if _lib().oracle_forward_cached(self._p, _dptr(img), _dptr(out)) != 0:
+                raise MemoryError("oracle_forward_cached: frame table allocation failed")
+        else:
+            _lib().oracle_forward(self._p, _dptr(img), _dptr(out), int(bool(dense)))
         return out
 
-    def back(self, sino, dense=False) -> np.ndarray:
+    def back(self, sino, dense=False, cached=False) -> np.ndarray:
+        """A^T y, with the same options as forward."""
         sino = np.ascontiguousarray(sino, dtype=np.float64).reshape(self.n_views, self.n_det)
         out = np.empty((self.ny, self.nx), dtype=np.float64)
-        _lib().oracle_back(self._p, _dptr(sino), _dptr(out), int(bool(dense)))
+        if cached and not dense:
+            if _lib().oracle_back_cached(self._p, _dptr(sino), _dptr(out)) != 0:
+                raise MemoryError("oracle_back_cached: frame table allocation failed")
+        else:
+            _lib().oracle_back(self._p, _dptr(sino), _dptr(out), int(bool(dense)))
         return out
 
     def forward_ray(self, img, v, m) -> float:

@@ -210,9 +210,32 @@ static void make_ray(const oracle_geom *g, int v, int m, ray_frame *r)
     }
 }
 
-/* The quantities eq. (18) is evaluated with, for ray (v, m) and pixel (i, j):
- * sp = s' (signed offset of the pixel centre from the ray), zeta1, zeta2 (the
- * pixel directions projected on w_perp) and taup = tau' (eq. (17)). */
+/* The quantities eq. (18) is evaluated with, for the ray with frame r and the
+ * pixel centred at k: sp = s' (signed offset of the pixel centre from the
+ * ray), zeta1, zeta2 (the pixel directions projected on w_perp) and
+ * taup = tau' (eq. (17)). */
+static void terms_from_frame(const oracle_geom *g, const ray_frame *r, const double k[2],
+                             double *sp, double *zeta1, double *zeta2, double *taup,
+                             double *depth)
+{
+    const double dk[2] = {k[0] - r->p[0], k[1] - r->p[1]};
+    const double s_off = r->wp[0] * dk[0] + r->wp[1] * dk[1];
+    const double L = r->w[0] * dk[0] + r->w[1] * dk[1];
+    *sp = s_off;
+    *zeta1 = g->pixel * r->wp[0];     /* R_{v perp} xi_1, xi_1 = (delta, 0) */
+    *zeta2 = g->pixel * r->wp[1];     /* R_{v perp} xi_2, xi_2 = (0, delta) */
+    if (g->mode == ORACLE_PARALLEL) {
+        *taup = g->det_width;
+    } else {
+        /* perspective division of each edge, then scaling to depth L */
+        const double t_hi = r->edge_hi[0] / r->edge_hi[1];
+        const double t_lo = r->edge_lo[0] / r->edge_lo[1];
+        *taup = L * (t_hi - t_lo);
+    }
+    if (depth) *depth = L;
+}
+
+/* The same quantities for ray (v, m) and pixel (i, j). */
 void oracle_entry_terms(const oracle_geom *g, int v, int m, int i, int j,
                         double *sp, double *zeta1, double *zeta2, double *taup,
                         double *depth)
@@ -221,21 +244,7 @@ void oracle_entry_terms(const oracle_geom *g, int v, int m, int i, int j,
     make_ray(g, v, m, &r);
     double k[2];
     pixel_centre(g, i, j, k);
-    const double dk[2] = {k[0] - r.p[0], k[1] - r.p[1]};
-    const double s_off = r.wp[0] * dk[0] + r.wp[1] * dk[1];
-    const double L = r.w[0] * dk[0] + r.w[1] * dk[1];
-    *sp = s_off;
-    *zeta1 = g->pixel * r.wp[0];      /* R_{v perp} xi_1, xi_1 = (delta, 0) */
-    *zeta2 = g->pixel * r.wp[1];      /* R_{v perp} xi_2, xi_2 = (0, delta) */
-    if (g->mode == ORACLE_PARALLEL) {
-        *taup = g->det_width;
-    } else {
-        /* perspective division of each edge, then scaling to depth L */
-        const double t_hi = r.edge_hi[0] / r.edge_hi[1];
-        const double t_lo = r.edge_lo[0] / r.edge_lo[1];
-        *taup = L * (t_hi - t_lo);
-    }
-    if (depth) *depth = L;
+    terms_from_frame(g, &r, k, sp, zeta1, zeta2, taup, depth);
 }
 
 /* Matrix entry A_{(v,m),(i,j)} = delta^2 * M_[zeta1, zeta2, tau'](s'). */
@@ -246,18 +255,14 @@ double oracle_entry(const oracle_geom *g, int v, int m, int i, int j)
     return g->pixel * g->pixel * oracle_box3(sp, z1, z2, tp);
 }
 
-/* Candidate cells of pixel (i, j) in view v: every cell whose bin meets the
- * interval spanned by the detector shadows of the pixel's four corners,
- * widened by one extra cell on each side.  The shadow of a point x is where
- * the line from the source through x meets the detector. */
-static void candidate_cells(const oracle_geom *g, int v, int i, int j,
-                            int *m_lo, int *m_hi)
+/* Candidate cells of the pixel centred at k in the view with source direction
+ * u and detector axis e: every cell whose bin meets the interval spanned by
+ * the detector shadows of the pixel's four corners, widened by one extra cell
+ * on each side.  The shadow of a point x is where the line from the source
+ * through x meets the detector. */
+static void candidate_cells_dirs(const oracle_geom *g, const double u[2], const double e[2],
+                                 const double k[2], int *m_lo, int *m_hi)
 {
-    const double th = g->angles[v];
-    const double u[2] = {cos(th), sin(th)};
-    const double e[2] = {sin(th), -cos(th)};
-    double k[2];
-    pixel_centre(g, i, j, k);
     double smin = INFINITY, smax = -INFINITY;
     for (int c = 0; c < 4; ++c) {
         const double x = k[0] + ((c & 1) ? 0.5 : -0.5) * g->pixel;
@@ -282,6 +287,18 @@ static void candidate_cells(const oracle_geom *g, int v, int i, int j,
     if (b > g->n_det - 1) b = g->n_det - 1;
     *m_lo = (int)a;
     *m_hi = (int)b;
+}
+
+/* Candidate cells of pixel (i, j) in view v. */
+static void candidate_cells(const oracle_geom *g, int v, int i, int j,
+                            int *m_lo, int *m_hi)
+{
+    const double th = g->angles[v];
+    const double u[2] = {cos(th), sin(th)};
+    const double e[2] = {sin(th), -cos(th)};
+    double k[2];
+    pixel_centre(g, i, j, k);
+    candidate_cells_dirs(g, u, e, k, m_lo, m_hi);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -376,6 +393,92 @@ void oracle_back_views(const oracle_geom *g, const double *sino, double *img,
     sub.angles = g->angles + v0;
     sub.n_views = v1 - v0;
     oracle_back(&sub, sino + (size_t)v0 * g->n_det, img, 0);
+}
+
+/* The frame of every ray, [n_views][n_det] (NULL if it cannot be allocated). */
+static ray_frame *all_frames(const oracle_geom *g)
+{
+    const size_t nr = (size_t)g->n_views * g->n_det;
+    ray_frame *f = malloc(nr * sizeof(ray_frame));
+    if (!f) return NULL;
+    #pragma omp parallel for schedule(static)
+    for (int v = 0; v < g->n_views; ++v)
+        for (int m = 0; m < g->n_det; ++m)
+            make_ray(g, v, m, &f[(size_t)v * g->n_det + m]);
+    return f;
+}
+
+static double entry_from_frame(const oracle_geom *g, const ray_frame *r, const double k[2])
+{
+    double sp, z1, z2, tp;
+    terms_from_frame(g, r, k, &sp, &z1, &z2, &tp, NULL);
+    return g->pixel * g->pixel * oracle_box3(sp, z1, z2, tp);
+}
+
+/* oracle_forward and oracle_back (with pruning) with every ray frame
+ * (make_ray) and every view's (cos t, sin t) computed once per call instead of
+ * once per entry.  The loops, the entry arithmetic and the summation order
+ * are theirs, so the results are bitwise the same; only the repeated
+ * evaluation of identical values is saved.  Used where full-size scans are
+ * projected many times (the stored large SIRT iterate).  Each returns 0, or
+ * -1 if its tables cannot be allocated. */
+int oracle_forward_cached(const oracle_geom *g, const double *img, double *sino)
+{
+    const int nv = g->n_views, nd = g->n_det;
+    ray_frame *f = all_frames(g);
+    if (!f) return -1;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int v = 0; v < nv; ++v) {
+        const double th = g->angles[v];
+        const double u[2] = {cos(th), sin(th)};
+        const double e[2] = {sin(th), -cos(th)};
+        const ray_frame *fv = f + (size_t)v * nd;
+        double *row = sino + (size_t)v * nd;
+        for (int m = 0; m < nd; ++m) row[m] = 0.0;
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                const double c = img[(size_t)j * g->nx + i];
+                double k[2];
+                pixel_centre(g, i, j, k);
+                int lo, hi;
+                candidate_cells_dirs(g, u, e, k, &lo, &hi);
+                for (int m = lo; m <= hi; ++m)
+                    row[m] += entry_from_frame(g, &fv[m], k) * c;
+            }
+    }
+    free(f);
+    return 0;
+}
+
+int oracle_back_cached(const oracle_geom *g, const double *sino, double *img)
+{
+    const int nx = g->nx, ny = g->ny, nv = g->n_views, nd = g->n_det;
+    ray_frame *f = all_frames(g);
+    double *dirs = malloc((size_t)nv * 4 * sizeof(double));
+    if (!f || !dirs) { free(f); free(dirs); return -1; }
+    for (int v = 0; v < nv; ++v) {
+        const double th = g->angles[v];
+        dirs[4 * v + 0] = cos(th); dirs[4 * v + 1] = sin(th);
+        dirs[4 * v + 2] = sin(th); dirs[4 * v + 3] = -cos(th);
+    }
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double k[2];
+            pixel_centre(g, i, j, k);
+            double acc = 0.0;
+            for (int v = 0; v < nv; ++v) {
+                int lo, hi;
+                candidate_cells_dirs(g, dirs + 4 * v, dirs + 4 * v + 2, k, &lo, &hi);
+                const ray_frame *fv = f + (size_t)v * nd;
+                for (int m = lo; m <= hi; ++m)
+                    acc += entry_from_frame(g, &fv[m], k) * sino[(size_t)v * nd + m];
+            }
+            img[(size_t)j * nx + i] = acc;
+        }
+    free(f);
+    free(dirs);
+    return 0;
 }
 
 /* Number of (ray, pixel) pairs whose entry is non-zero. */

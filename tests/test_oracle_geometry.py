@@ -201,16 +201,36 @@ def test_mirror_symmetry(oracle_mod):
     assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
 
 
+@pytest.mark.parametrize("mode", ["flat", "arc", "parallel"])
 @pytest.mark.parametrize("n,dsc,dsd,tau,nd", [(8, 20.0, 40.0, 1.0, 24), (16, 30.0, 45.0, 0.7, 48),
                                               (16, 14.0, 40.0, 1.3, 64)])
-def test_pruned_equals_dense(oracle_mod, n, dsc, dsd, tau, nd):
+def test_pruned_equals_dense(oracle_mod, n, dsc, dsd, tau, nd, mode):
+    """Candidate-cell pruning drops no non-zero entry, for every beam shape
+    (the sums are taken in the same order, so the results are bitwise equal)."""
     rng = np.random.default_rng(n)
     angs = np.concatenate([[0.0, math.pi / 2, math.pi / 4], rng.uniform(0, 2 * math.pi, 9)])
-    g = oracle_mod.Geometry(n, n, 1.0, dsc, dsd, angs, nd, tau)
+    md = {"flat": oracle_mod.FAN_FLAT, "arc": oracle_mod.FAN_ARC, "parallel": oracle_mod.PARALLEL}[mode]
+    g = oracle_mod.Geometry(n, n, 1.0, dsc, dsd, angs, nd, tau, mode=md)
     c = phantoms.uniform((n, n), 41).astype(np.float64)
     y = phantoms.uniform((len(angs), nd), 42).astype(np.float64)
-    assert np.array_equal(g.forward(c), g.forward(c, dense=True))
+    fy = g.forward(c)
+    assert np.count_nonzero(fy) >= 10 * len(angs)
+    assert np.array_equal(fy, g.forward(c, dense=True))
     assert np.array_equal(g.back(y), g.back(y, dense=True))
+
+
+@pytest.mark.parametrize("mode", ["flat", "arc", "parallel"])
+def test_cached_frames_equal_plain_operators(oracle_mod, mode):
+    """The cached-frame operators (used for the stored full-size SIRT
+    iterate) are the pruned operators bitwise, also with pitch != width, a
+    pixel size != 1 and a non-square grid."""
+    md = {"flat": oracle_mod.FAN_FLAT, "arc": oracle_mod.FAN_ARC, "parallel": oracle_mod.PARALLEL}[mode]
+    angs = phantoms.view_angles(41) + 0.05
+    g = oracle_mod.Geometry(40, 34, 0.9, 60.0, 110.0, angs, 77, 1.3, det_spacing=1.1, mode=md)
+    c = phantoms.uniform((34, 40), 43).astype(np.float64)
+    y = phantoms.uniform((41, 77), 44).astype(np.float64)
+    assert np.array_equal(g.forward(c), g.forward(c, cached=True))
+    assert np.array_equal(g.back(y), g.back(y, cached=True))
 
 
 def test_pruned_equals_dense_small_scan(oracle_mod):

@@ -60,3 +60,22 @@ def test_sirt_residual_decreases_and_fits_consistent_data(oracle_mod):
         assert wres <= prev * (1 + 1e-12)
         prev = wres
     assert prev < 1e-2 * float(np.sum(R * y * y))
+
+
+def test_golden_script_steps_equal_oracle_sirt(oracle_mod):
+    """The stored full-size SIRT iterate is written by stepping the oracle's
+    cached-frame operators one iteration at a time (so the run can be
+    checkpointed); those steps equal the oracle's own SIRT loop bitwise."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_sirt_golden as mk
+    from paper_1907_10526_amd import workloads
+    s = workloads.SMALL
+    g = oracle_mod.Geometry(**s.kwargs())
+    y = phantoms.uniform((s.n_views, s.n_det), 5, 0.0, 4.0).astype(np.float64)
+    R, C = mk.sirt_weights(g)
+    x = np.zeros((s.n, s.n))
+    for _ in range(3):
+        x = mk.sirt_step(g, x, y, R, C)
+    assert np.array_equal(x, g.sirt(y, 3))
