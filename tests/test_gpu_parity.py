@@ -254,3 +254,29 @@ def test_rejects_host_pointer(fp, torch_cuda):
     # the geometry still works afterwards
     y = gg.forward(torch.zeros((s.n, s.n), device="cuda"))
     assert float(y.abs().max()) == 0.0
+
+
+def test_medium_full_elementwise(oracle_mod, fp, torch_cuda):
+    """The 512 x 512, 720-view, 1024-cell pair compared element by element
+    with the oracle's full forward and back projections (every ray and
+    every pixel): relative L2 <= 1e-5 and the largest deviation <= 1e-5 of
+    the largest value; the GPU's non-zero count (the unit the throughput is
+    priced in) equals the oracle's to 1e-4."""
+    torch = torch_cuda
+    s = workloads.MEDIUM
+    og, gg = _pair(oracle_mod, fp, **s.kwargs())
+    img = workloads.phantom(s)
+    y = gg.forward(_to_gpu(torch, img)).cpu().numpy()
+    y_ref = og.forward(img.astype(np.float64), cached=True)
+    ef, mf = rel_l2(y, y_ref), float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+    sino = phantoms.uniform((s.n_views, s.n_det), 13, 0.0, 1.0)
+    z = gg.back(_to_gpu(torch, sino)).cpu().numpy()
+    z_ref = og.back(sino.astype(np.float64), cached=True)
+    eb, mb = rel_l2(z, z_ref), float(np.abs(z - z_ref).max() / np.abs(z_ref).max())
+    print(f"medium full: forward rel-L2 {ef:.3e} (max {mf:.3e} of peak), "
+          f"back rel-L2 {eb:.3e} (max {mb:.3e} of peak)", flush=True)
+    assert ef <= TOL and mf <= TOL
+    assert eb <= TOL and mb <= TOL
+    got, ref = gg.count_nonzero(), og.count_nonzero()
+    print(f"medium non-zero entries: GPU {got}, oracle {ref}", flush=True)
+    assert abs(got - ref) <= 1e-4 * ref, (got, ref)
