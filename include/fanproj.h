@@ -252,6 +252,19 @@ fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream);
  * tables and the SIRT weights.  0 for NULL.  Serving code uses it for admission by free memory. */
 size_t fp_geometry_device_bytes(const fp_geometry *g);
 
+/* 1 if the geometry's FP32 projections and SIRT steps run in the
+ * quarter-turn form, else 0 (also for NULL).  A square image whose views
+ * come in quadruples a quarter turn apart (view v + k n_views/4 at the angle
+ * of view v plus k pi/2 for k < 4, to 1e-13 rad; e.g. n_views a multiple of
+ * 4 spaced uniformly over 2 pi) is unchanged by a quarter turn of the whole
+ * scan, so entry A_{(v + k n_views/4, m), R^k p} equals A_{(v, m), p} with R
+ * the quarter turn of the pixel grid (eq. (18) depends only on the ray and
+ * the pixel's position relative to it).  That form evaluates each entry once
+ * for the four views and applies it to the four quarter-turned images; the
+ * results equal the plain form's to FP32 rounding.  The FP64 calls and the
+ * reference projector always evaluate every view. */
+int32_t fp_geometry_quarter_turn(const fp_geometry *g);
+
 /* Text for the last non-OK status returned on the calling thread ("" if
  * none).  The pointer stays valid until the thread's next fanproj call. */
 const char *fp_last_error(void);

@@ -15,28 +15,6 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// Makes the geometry's device current for the duration of a call and
-// restores the caller's device afterwards.
-class DeviceGuard {
-  public:
-    explicit DeviceGuard(int dev) {
-        err_ = hipGetDevice(&prev_);
-        if (err_ == hipSuccess && prev_ != dev) {
-            err_ = hipSetDevice(dev);
-            switched_ = err_ == hipSuccess;
-        }
-    }
-    ~DeviceGuard() {
-        if (switched_) (void)hipSetDevice(prev_);
-    }
-    hipError_t status() const { return err_; }
-
-  private:
-    int prev_ = 0;
-    bool switched_ = false;
-    hipError_t err_ = hipSuccess;
-};
-
 // A pointer is accepted when HIP knows it as device (or managed) memory of
 // the geometry's device.
 fp_status check_device_ptr(const void *p, int dev, const char *what) {
@@ -71,6 +49,12 @@ int chunk_for(int remaining, int max_nb) {
 }
 
 int back_max_chunk(const DevGeom &g) { return std::max(back_max_batch<float>(g), 1); }
+
+// Images per launch of the quarter-turn forms (the back kernel holds four
+// view quarters per image).
+int quarter_max_chunk(const fp_geometry *g) {
+    return std::max(1, std::min(kQuarterMaxChunk, back_max_batch<float>(g->dev_quarter) / 4));
+}
 
 // Device scratch of the launches (the forward's padded image copies, the
 // back projection's view-group partials, the grouped SIRT buffers).  Each
@@ -224,6 +208,22 @@ fp_status forward_impl(const fp_geometry *gc, const Real *image, Real *sino, int
     }
     const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if constexpr (sizeof(Real) == sizeof(float)) {
+        if (g->quarter) {
+            const int max_nb = chunk_for(batch, quarter_max_chunk(g));
+            Scratch work(g->device, forward_quarter_work_bytes(g->dev_quarter, max_nb), s);
+            if (work.status() != hipSuccess) return scratch_error(fn, work.status());
+            for (int b0 = 0; b0 < batch;) {
+                const int nb = chunk_for(batch - b0, max_nb);
+                hipError_t e = launch_forward_quarter(g->dev_quarter, FwdMode::kPlain, nb,
+                                                      image + b0 * np, work.get(), sino + b0 * nr,
+                                                      nullptr, nullptr, s);
+                if (e != hipSuccess) return device_error(fn, e);
+                b0 += nb;
+            }
+            return FP_OK;
+        }
+    }
     const int max_nb = chunk_for(batch, kMaxBatchChunk);
     Scratch work(g->device, forward_work_bytes<Real>(g->dev, max_nb), s);
     if (work.status() != hipSuccess) return scratch_error(fn, work.status());
@@ -260,6 +260,22 @@ fp_status back_impl(const fp_geometry *gc, const Real *sino, Real *image, int32_
     }
     const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if constexpr (sizeof(Real) == sizeof(float)) {
+        if (g->quarter) {
+            const int qnb = chunk_for(batch, quarter_max_chunk(g));
+            Scratch partial(g->device, back_quarter_work_bytes(g->dev_quarter, qnb), s);
+            if (partial.status() != hipSuccess) return scratch_error(fn, partial.status());
+            for (int b0 = 0; b0 < batch;) {
+                const int nb = chunk_for(batch - b0, qnb);
+                hipError_t e = launch_back_quarter(g->dev_quarter, BackMode::kPlain, nb,
+                                                   sino + b0 * nr, image + b0 * np, partial.get(),
+                                                   nullptr, 0.0f, s);
+                if (e != hipSuccess) return device_error(fn, e);
+                b0 += nb;
+            }
+            return FP_OK;
+        }
+    }
     const size_t pbytes = back_work_bytes<Real>(g->dev, chunk_for(batch, max_nb));
     Scratch partial(g->device, std::max<size_t>(pbytes, 256), s);
     if (partial.status() != hipSuccess) return scratch_error(fn, partial.status());
@@ -333,45 +349,98 @@ extern "C" fp_status fp_back_reference(const fp_geometry *g, const double *sino,
     return reference_impl(g, false, sino, image, batch, quad_points, stream, "fp_back_reference");
 }
 
+namespace fanproj {
+
+fp_status sirt_check(const fp_geometry *g, const float *image, const float *sino_meas,
+                     float relaxation, const float *work, int32_t batch, const char *fn) {
+    fp_status st = check_call(g, batch, fn);
+    if (st != FP_OK) return st;
+    if (!std::isfinite(relaxation)) {
+        set_error(std::string(fn) + ": relaxation must be finite");
+        return FP_ERR_INVALID_ARG;
+    }
+    if ((st = check_device_ptr(image, g->device, (std::string(fn) + ": image").c_str())) != FP_OK)
+        return st;
+    if ((st = check_device_ptr(sino_meas, g->device, (std::string(fn) + ": sino_meas").c_str())) !=
+        FP_OK)
+        return st;
+    return check_device_ptr(work, g->device, (std::string(fn) + ": work").c_str());
+}
+
+int sirt_max_chunk(const fp_geometry *g, bool quarter) {
+    if (quarter) return quarter_max_chunk(g);
+    return std::min(kMaxBatchChunk, back_max_chunk(g->dev));
+}
+
+size_t sirt_scratch_bytes(const fp_geometry *g, int nb, bool quarter, size_t *partial_offset) {
+    const size_t copies = (quarter ? forward_quarter_work_bytes(g->dev_quarter, nb)
+                                   : forward_work_bytes<float>(g->dev, nb));
+    const size_t aligned = (copies + 255) / 256 * 256;
+    if (partial_offset) *partial_offset = aligned;
+    return aligned + (quarter ? back_quarter_work_bytes(g->dev_quarter, nb)
+                              : back_work_bytes<float>(g->dev, nb));
+}
+
+fp_status sirt_step_launch(const fp_geometry *g, float *image, const float *sino_meas,
+                           float relaxation, float *work, int32_t batch, int max_nb, bool quarter,
+                           void *scratch, hipStream_t s, const char *fn) {
+    const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
+    size_t poff = 0;
+    (void)sirt_scratch_bytes(g, max_nb, quarter, &poff);
+    float *copies = static_cast<float *>(scratch);
+    float *partial = reinterpret_cast<float *>(static_cast<char *>(scratch) + poff);
+    if (quarter) {
+        for (int b0 = 0; b0 < batch;) {
+            const int nb = chunk_for(batch - b0, max_nb);
+            hipError_t e = launch_forward_quarter(g->dev_quarter, FwdMode::kSirtResidual, nb,
+                                                  image + b0 * np, copies, work + b0 * nr,
+                                                  sino_meas + b0 * nr, g->row_w, s);
+            if (e != hipSuccess) return device_error((std::string(fn) + ": forward launch").c_str(), e);
+            e = launch_back_quarter(g->dev_quarter, BackMode::kSirtUpdate, nb, work + b0 * nr,
+                                    image + b0 * np, partial, g->col_w, relaxation, s);
+            if (e != hipSuccess) return device_error((std::string(fn) + ": back launch").c_str(), e);
+            b0 += nb;
+        }
+        return FP_OK;
+    }
+    const bool use_partial = back_work_bytes<float>(g->dev, 1) > 0;
+    for (int b0 = 0; b0 < batch;) {
+        const int nb = chunk_for(batch - b0, max_nb);
+        hipError_t e = launch_forward<float>(g->dev, FwdMode::kSirtResidual, nb, image + b0 * np,
+                                             copies, work + b0 * nr, nullptr, sino_meas + b0 * nr,
+                                             g->row_w, s);
+        if (e != hipSuccess) return device_error((std::string(fn) + ": forward launch").c_str(), e);
+        e = launch_back<float>(g->dev, BackMode::kSirtUpdate, nb, work + b0 * nr, image + b0 * np,
+                               use_partial ? partial : nullptr, g->col_w, relaxation, s);
+        if (e != hipSuccess) return device_error((std::string(fn) + ": back launch").c_str(), e);
+        b0 += nb;
+    }
+    return FP_OK;
+}
+
+}  // namespace fanproj
+
 extern "C" fp_status fp_sirt_step(const fp_geometry *g_const, float *image, const float *sino_meas,
                                   float relaxation, float *work, int32_t batch, void *stream) {
     clear_error();
     fp_status st = check_call(g_const, batch, "fp_sirt_step");
     if (st != FP_OK) return st;
-    if (!std::isfinite(relaxation)) {
-        set_error("fp_sirt_step: relaxation must be finite");
-        return FP_ERR_INVALID_ARG;
-    }
     // The weights are the only state a geometry acquires after creation.
     fp_geometry *g = const_cast<fp_geometry *>(g_const);
     DeviceGuard guard(g->device);
     if (guard.status() != hipSuccess)
         return device_error("fp_sirt_step: hipSetDevice", guard.status());
-    if ((st = check_device_ptr(image, g->device, "fp_sirt_step: image")) != FP_OK) return st;
-    if ((st = check_device_ptr(sino_meas, g->device, "fp_sirt_step: sino_meas")) != FP_OK) return st;
-    if ((st = check_device_ptr(work, g->device, "fp_sirt_step: work")) != FP_OK) return st;
+    if ((st = sirt_check(g, image, sino_meas, relaxation, work, batch, "fp_sirt_step")) != FP_OK)
+        return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = ensure_weights(g, s)) != FP_OK) return st;
-    const size_t np = (size_t)g->nx * g->ny, nr = (size_t)g->nv * g->nd;
-    const int back_nb = back_max_chunk(g->dev);
-    const int max_nb = chunk_for(batch, std::min(kMaxBatchChunk, back_nb));
-    Scratch scratch(g->device, forward_work_bytes<float>(g->dev, max_nb), s);
+    const bool quarter = g->quarter;
+    const int max_nb = chunk_for(batch, sirt_max_chunk(g, quarter));
+    Scratch scratch(g->device,
+                    std::max<size_t>(sirt_scratch_bytes(g, max_nb, quarter, nullptr), 256), s);
     if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step", scratch.status());
-    const size_t pbytes = back_work_bytes<float>(g->dev, max_nb);
-    Scratch partial(g->device, std::max<size_t>(pbytes, 256), s);
-    if (partial.status() != hipSuccess) return scratch_error("fp_sirt_step", partial.status());
-    for (int b0 = 0; b0 < batch;) {
-        const int nb = chunk_for(batch - b0, std::min(kMaxBatchChunk, back_nb));
-        hipError_t e = launch_forward<float>(g->dev, FwdMode::kSirtResidual, nb, image + b0 * np,
-                                      scratch.get(), work + b0 * nr, nullptr, sino_meas + b0 * nr,
-                                      g->row_w, s);
-        if (e != hipSuccess) return device_error("fp_sirt_step: forward launch", e);
-        e = launch_back<float>(g->dev, BackMode::kSirtUpdate, nb, work + b0 * nr, image + b0 * np,
-                        pbytes ? partial.get() : nullptr, g->col_w, relaxation, s);
-        if (e != hipSuccess) return device_error("fp_sirt_step: back launch", e);
-        b0 += nb;
-    }
-    return FP_OK;
+    return sirt_step_launch(g, image, sino_meas, relaxation, work, batch, max_nb, quarter,
+                            scratch.raw(), s, "fp_sirt_step");
 }
 
 extern "C" fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream) {
@@ -417,6 +486,18 @@ extern "C" fp_status fp_sirt_prepare(const fp_geometry *gc, void *stream) {
     return ensure_weights(g, static_cast<hipStream_t>(stream));
 }
 
+namespace {
+// Scratch of one job of a grouped step, in the job's form.
+size_t multi_copies_bytes(const fp_geometry *g) {
+    return g->quarter ? forward_quarter_work_bytes(g->dev_quarter, 1)
+                      : forward_work_bytes<float>(g->dev, 1);
+}
+size_t multi_partial_bytes(const fp_geometry *g) {
+    return g->quarter ? back_quarter_work_bytes(g->dev_quarter, 1)
+                      : back_work_bytes<float>(g->dev, 1);
+}
+}  // namespace
+
 extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs, void *stream) {
     clear_error();
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) {
@@ -453,40 +534,48 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
         if ((st = check_device_ptr(J.sino_meas, dev, (tag + " sino_meas").c_str())) != FP_OK) return st;
         if ((st = check_device_ptr(J.work, dev, (tag + " work").c_str())) != FP_OK) return st;
         if ((st = ensure_weights(const_cast<fp_geometry *>(J.geometry), s)) != FP_OK) return st;
-        scratch_bytes += (forward_work_bytes<float>(J.geometry->dev, 1) + 255) / 256 * 256;
-        scratch_bytes += (back_work_bytes<float>(J.geometry->dev, 1) + 255) / 256 * 256;
+        scratch_bytes += (multi_copies_bytes(J.geometry) + 255) / 256 * 256;
+        scratch_bytes += (multi_partial_bytes(J.geometry) + 255) / 256 * 256;
     }
     Scratch scratch(dev, scratch_bytes, s);
     if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step_multi", scratch.status());
     char *base = static_cast<char *>(scratch.raw());
     size_t off = 0;
-    for (int k0 = 0; k0 < n_jobs; k0 += kMaxJobsPerLaunch) {
-        MultiArgs args{};
-        args.n = std::min(kMaxJobsPerLaunch, n_jobs - k0);
-        unsigned fwd = 0;
-        for (int k = 0; k < args.n; ++k) {
-            const fp_sirt_job &J = jobs[k0 + k];
-            const fp_geometry *g = J.geometry;
-            MultiJob &M = args.job[k];
-            M.g = g->dev;
-            const int nrows = std::max(g->nx, g->ny);
-            M.copies = reinterpret_cast<float *>(base + off);
-            off += (forward_work_bytes<float>(g->dev, 1) + 255) / 256 * 256;
-            M.partial = reinterpret_cast<float *>(base + off);
-            off += (back_work_bytes<float>(g->dev, 1) + 255) / 256 * 256;
-            M.image = J.image;
-            M.image_out = J.image;
-            M.y_meas = J.sino_meas;
-            M.work = J.work;
-            M.row_w = g->row_w;
-            M.col_w = g->col_w;
-            M.relaxation = J.relaxation;
-            M.fwd_begin = fwd;
-            fwd += (unsigned)g->nv * (unsigned)((g->nd + kFwdThreads - 1) / kFwdThreads);
+    // grouped launches of up to kMaxJobsPerLaunch jobs of one form: the
+    // quarter-turn jobs first, then the plain ones (each job's order within
+    // its form kept)
+    for (int form = 1; form >= 0; --form) {
+        std::vector<int> idx;
+        for (int k = 0; k < n_jobs; ++k)
+            if ((int)jobs[k].geometry->quarter == form) idx.push_back(k);
+        for (size_t k0 = 0; k0 < idx.size(); k0 += kMaxJobsPerLaunch) {
+            MultiArgs args{};
+            args.n = (int)std::min<size_t>(kMaxJobsPerLaunch, idx.size() - k0);
+            args.quarter = form;
+            unsigned fwd = 0;
+            for (int k = 0; k < args.n; ++k) {
+                const fp_sirt_job &J = jobs[idx[k0 + k]];
+                const fp_geometry *g = J.geometry;
+                MultiJob &M = args.job[k];
+                M.g = form ? g->dev_quarter : g->dev;
+                M.copies = reinterpret_cast<float *>(base + off);
+                off += (multi_copies_bytes(g) + 255) / 256 * 256;
+                M.partial = reinterpret_cast<float *>(base + off);
+                off += (multi_partial_bytes(g) + 255) / 256 * 256;
+                M.image = J.image;
+                M.image_out = J.image;
+                M.y_meas = J.sino_meas;
+                M.work = J.work;
+                M.row_w = g->row_w;
+                M.col_w = g->col_w;
+                M.relaxation = J.relaxation;
+                M.fwd_begin = fwd;
+                fwd += (unsigned)M.g.nv * (unsigned)((M.g.nd + kFwdThreads - 1) / kFwdThreads);
+            }
+            args.fwd_blocks = fwd;
+            hipError_t e = launch_sirt_multi(args, s);
+            if (e != hipSuccess) return device_error("fp_sirt_step_multi: launch", e);
         }
-        args.fwd_blocks = fwd;
-        hipError_t e = launch_sirt_multi(args, s);
-        if (e != hipSuccess) return device_error("fp_sirt_step_multi: launch", e);
     }
     return FP_OK;
 }

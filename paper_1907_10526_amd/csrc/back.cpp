@@ -35,6 +35,27 @@ hipError_t launch_back(const DevGeom &g, BackMode mode, int nb, const Real *sino
     return hipErrorInvalidValue;
 }
 
+size_t back_quarter_work_bytes(const DevGeom &g, int nb) {
+    return (size_t)g.back_groups * 4 * nb * g.nx * g.ny * sizeof(float);
+}
+
+hipError_t launch_back_quarter(const DevGeom &g, BackMode mode, int nb, const float *sino,
+                               float *img, float *partial, const float *col_w, float relaxation,
+                               hipStream_t stream) {
+    switch (g.beam) {
+        case FP_FAN_FLAT:
+            return launch_back_quarter_beam<FP_FAN_FLAT>(g, mode, nb, sino, img, partial, col_w,
+                                                         relaxation, stream);
+        case FP_FAN_ARC:
+            return launch_back_quarter_beam<FP_FAN_ARC>(g, mode, nb, sino, img, partial, col_w,
+                                                        relaxation, stream);
+        case FP_PARALLEL:
+            return launch_back_quarter_beam<FP_PARALLEL>(g, mode, nb, sino, img, partial, col_w,
+                                                         relaxation, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
 #define FANPROJ_INSTANTIATE(Real)                                                                  \
     template int back_max_batch<Real>(const DevGeom &);                                            \
     template size_t back_work_bytes<Real>(const DevGeom &, int);                                   \

@@ -1,4 +1,5 @@
-// Back projection kernels for the parallel beams, FP32.
+// Back projection kernels for the parallel beam, FP32, and their quarter-turn form.
 #include "back_launch.h"
 
 FANPROJ_INSTANTIATE_BACK(float, FP_PARALLEL)
+FANPROJ_INSTANTIATE_BACK_QUARTER(FP_PARALLEL)

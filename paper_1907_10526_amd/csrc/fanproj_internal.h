@@ -189,6 +189,31 @@ hipError_t launch_back_beam(const DevGeom &g, BackMode mode, int nb, const Real 
 template <typename Real>
 int back_max_batch(const DevGeom &g);
 
+// Quarter-turn forms (FP32) for a square image whose views come in
+// quadruples a quarter turn apart (view v + k nv at angle t_v + k pi/2, nv a
+// quarter of the views, k < 4): g describes the first quarter of the views,
+// the tables of which are a prefix of the full geometry's.  The entries of
+// view v + k nv on an image equal those of view v on the image turned by k
+// quarter turns, so each entry is evaluated once for four views.  Sinograms
+// keep their full [nb][4 nv][nd] layout; at most kQuarterMaxChunk images per
+// launch.  launch_forward_quarter: modes kPlain and kSirtResidual (row_w the
+// full view set's), `work` of forward_quarter_work_bytes(g, nb) bytes for
+// four padded copies per image.  launch_back_quarter: modes kPlain and
+// kSirtUpdate, `partial` of back_quarter_work_bytes(g, nb) bytes.
+constexpr int kQuarterMaxChunk = 2;
+size_t forward_quarter_work_bytes(const DevGeom &g, int nb);
+hipError_t launch_forward_quarter(const DevGeom &g, FwdMode mode, int nb, const float *img,
+                                  float *work, float *out, const float *y_meas,
+                                  const float *row_w, hipStream_t stream);
+size_t back_quarter_work_bytes(const DevGeom &g, int nb);
+hipError_t launch_back_quarter(const DevGeom &g, BackMode mode, int nb, const float *sino,
+                               float *img, float *partial, const float *col_w, float relaxation,
+                               hipStream_t stream);
+template <int BEAM>
+hipError_t launch_back_quarter_beam(const DevGeom &g, BackMode mode, int nb, const float *sino,
+                                    float *img, float *partial, const float *col_w,
+                                    float relaxation, hipStream_t stream);
+
 // Grouped SIRT step: several jobs, each with its own geometry; one launch
 // for the padded copies and one for the forward residuals of all of them,
 // then each job's back update.  Up to kMaxJobsPerLaunch job descriptors
@@ -208,12 +233,17 @@ struct MultiJob {
 };
 struct MultiArgs {
     int n;
+    // 1: every job in the quarter-turn form (g = the geometry's dev_quarter,
+    // copies of forward_quarter_work_bytes(g, 1) bytes, partial of
+    // back_quarter_work_bytes(g, 1)); 0: every job in the plain form
+    int quarter;
     unsigned fwd_blocks;
     MultiJob job[kMaxJobsPerLaunch];
 };
 static_assert(sizeof(MultiArgs) <= 4000, "kernel arguments must stay under 4 KB");
 // Launch the three phases for args.job[0 .. n) (multi.hip); copies/
-// partial/fwd_begin must be filled in (partial: back_work_bytes<float>(g, 1)
+// partial/fwd_begin must be filled in (plain form: copies of
+// forward_work_bytes<float>(g, 1) bytes, partial of back_work_bytes<float>(g, 1)
 // bytes).
 hipError_t launch_sirt_multi(const MultiArgs &args, hipStream_t stream);
 
@@ -225,6 +255,12 @@ struct fp_geometry {
     double pixel = 0, dsc = 0, dsd = 0, tau = 0, pitch = 0;
     std::vector<double> angles;
     fanproj::DevGeom dev{};
+    // Quarter-turn symmetry (nx == ny, views in quarter-turn quadruples):
+    // dev_quarter is dev restricted to the first quarter of the views (same
+    // tables, nv / 4 views, its own view-group count); FP32 projections and
+    // SIRT steps then run in the quarter-turn form.
+    bool quarter = false;
+    fanproj::DevGeom dev_quarter{};
     void *table_block = nullptr;   // one device allocation for the FP32 tables
     size_t table_bytes = 0;
     // FP64 per-ray tables, built on the first FP64 call.
@@ -241,6 +277,48 @@ struct fp_geometry {
 };
 
 namespace fanproj {
+// Makes the geometry's device current for the duration of a call and
+// restores the caller's device afterwards.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) {
+        err_ = hipGetDevice(&prev_);
+        if (err_ == hipSuccess && prev_ != dev) {
+            err_ = hipSetDevice(dev);
+            switched_ = err_ == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (switched_) (void)hipSetDevice(prev_);
+    }
+    DeviceGuard(const DeviceGuard &) = delete;
+    DeviceGuard &operator=(const DeviceGuard &) = delete;
+    hipError_t status() const { return err_; }
+
+  private:
+    int prev_ = 0;
+    bool switched_ = false;
+    hipError_t err_ = hipSuccess;
+};
+
+// The parts of the SIRT step shared by the SIRT entry points (abi.cpp).
+// sirt_check: the argument checks of fp_sirt_step (geometry, batch,
+// relaxation, device pointers).  `quarter` selects the quarter-turn form
+// (only for a geometry with g->quarter) or the plain one.  sirt_max_chunk:
+// the largest batch chunk one launch pair takes.  sirt_scratch_bytes: device
+// scratch one step needs for chunks of nb images (padded copies, then
+// view-group partials at *partial_offset).  sirt_step_launch: the launches,
+// in chunks of at most max_nb images, with `scratch` of
+// sirt_scratch_bytes(g, max_nb, quarter) bytes; the weights must have been
+// built.
+fp_status sirt_check(const fp_geometry *g, const float *image, const float *sino_meas,
+                     float relaxation, const float *work, int32_t batch, const char *fn);
+int sirt_max_chunk(const fp_geometry *g, bool quarter);
+size_t sirt_scratch_bytes(const fp_geometry *g, int nb, bool quarter, size_t *partial_offset);
+fp_status sirt_step_launch(const fp_geometry *g, float *image, const float *sino_meas,
+                           float relaxation, float *work, int32_t batch, int max_nb, bool quarter,
+                           void *scratch, hipStream_t s, const char *fn);
+
 // The reference projector (reference.hip): forward (true) or its adjoint
 // over `batch` images, FP64, `quad` Gauss-Legendre points per smooth piece.
 hipError_t launch_reference(const fp_geometry *g, bool forward, const double *in, double *out,

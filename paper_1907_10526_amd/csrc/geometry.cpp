@@ -17,6 +17,30 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 bool finite_positive(double x) { return std::isfinite(x) && x > 0.0; }
 
+// View groups of the back projection: added until about kBackGroupsPerCu
+// work-groups per compute unit are in flight, at most kBackMaxGroups and with
+// at least 8 views per group.
+int view_groups(size_t ntiles, int n_views, int cus) {
+    const long want = ((long)kBackGroupsPerCu * cus + (long)ntiles - 1) / (long)ntiles;
+    long groups = std::max(1L, std::min<long>(want, kBackMaxGroups));
+    while (groups > 1 && n_views / groups < 8) --groups;
+    return (int)groups;
+}
+
+// Whether the scan is unchanged by a quarter turn: a square grid and views
+// v + k (n_views / 4), k < 4, at the angle of view v plus k pi/2 (to 1e-13
+// rad, far below what FP32 entries resolve).  The quarter-turn forms of the
+// projections then evaluate each entry once for four views.
+bool quarter_turn_symmetric(int nx, int ny, int n_views, const double *angles) {
+    if (nx != ny || n_views % 4 != 0) return false;
+    const int q = n_views / 4;
+    for (int v = 0; v < n_views; ++v) {
+        const double d = angles[v] - angles[v % q] - (v / q) * (0.5 * M_PI);
+        if (!(std::fabs(std::remainder(d, 2.0 * M_PI)) <= 1e-13)) return false;
+    }
+    return true;
+}
+
 }  // namespace
 
 fp_status ensure_f64_tables(fp_geometry *g) {
@@ -255,11 +279,13 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
         (void)hipGetLastError();
         cus = 256;
     }
-    {
-        const long want = ((long)kBackGroupsPerCu * cus + (long)ntiles - 1) / (long)ntiles;
-        long groups = std::max(1L, std::min<long>(want, kBackMaxGroups));
-        while (groups > 1 && n_views / groups < 8) --groups;
-        d.back_groups = (int)groups;
+    d.back_groups = view_groups(ntiles, n_views, cus);
+    g->quarter = quarter_turn_symmetric(nx, ny, n_views, view_angles) &&
+                 back_max_batch<float>(d) >= 4;
+    if (g->quarter) {
+        g->dev_quarter = d;
+        g->dev_quarter.nv = n_views / 4;
+        g->dev_quarter.back_groups = view_groups(ntiles, n_views / 4, cus);
     }
     *out = g.release();
     return FP_OK;
@@ -288,3 +314,5 @@ extern "C" size_t fp_geometry_device_bytes(const fp_geometry *g) {
     if (!g) return 0;
     return g->table_bytes + g->f64_bytes + g->weight_bytes;
 }
+
+extern "C" int32_t fp_geometry_quarter_turn(const fp_geometry *g) { return g && g->quarter ? 1 : 0; }

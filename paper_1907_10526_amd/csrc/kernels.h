@@ -121,17 +121,22 @@ constexpr int kSumBlock = 32;        // views per partial sum of the back projec
 constexpr int kFwdBlockRows = 64;    // rows per block of the forward walk
 
 // ---------------------------------------------------------------------------
-// Padded image copies for the forward walk, row-major and transposed, each
-// with NR = max(nx, ny) rows of W = NR + 2 pad values (rows and values past
-// the image are zero, so a wave whose rays march along different axes can
-// walk the union of their row ranges with one clamp bound), interleaved row
-// by row: copies [nb][NR][2][W], so that row r of either copy is at one
-// address common to the wave plus a small per-lane offset (0 or W):
-//   row copy  (slot 0): pixel (i, j) at (j * 2 + 0) * W + pad + i
-//   col copy  (slot 1): pixel (i, j) at (i * 2 + 1) * W + pad + j
+// Padded image copies for the forward walk, each with NR = max(nx, ny) rows of
+// W = NR + 2 pad values (rows and values past the image are zero, so a wave
+// whose rays march along different axes can walk the union of their row
+// ranges with one clamp bound), interleaved row by row: copies [nb][NR][S][W],
+// so that row r of every copy is at one address common to the wave plus a
+// small per-lane offset (a multiple of W):
+//   slot 0, row copy:             pixel (i, j) at (j S + 0) W + pad + i
+//   slot 1, column copy:          pixel (i, j) at (i S + 1) W + pad + j
+// and, with S = 4, the same two of the image mirrored left to right (the
+// quarter-turn rotations of a square image read them, see forward_block):
+//   slot 2, mirrored row copy:    pixel (i, j) at (j S + 2) W + W - 1 - pad - i
+//   slot 3, mirrored column copy: pixel (i, j) at (i S + 3) W + W - 1 - pad - j
 // ---------------------------------------------------------------------------
-// Row copy (slot 0) of images [0, nb): work item e of the flattened copy.
-template <typename Real>
+// Row copies (slots 0 and 2) of images [0, nb): work item e of the flattened
+// row copy.
+template <typename Real, int S>
 __device__ __forceinline__ void pad_rows_body(const Real *__restrict__ img,
                                               Real *__restrict__ copies, int nx, int ny,
                                               int nrows, int nb, size_t first, size_t stride) {
@@ -139,17 +144,21 @@ __device__ __forceinline__ void pad_rows_body(const Real *__restrict__ img,
     const size_t total = (size_t)w * nrows * nb;
     for (size_t e = first; e < total; e += stride) {
         const size_t row = e / w;    // b * nrows + j
-        const int j = (int)(row % nrows), i = (int)(e % w) - kFwdPad;
+        const int x = (int)(e % w);
+        const int j = (int)(row % nrows), i = x - kFwdPad;
         const size_t b = row / nrows;
-        copies[row * 2 * w + e % w] =
+        const Real val =
             (i >= 0 && i < nx && j < ny) ? img[b * (size_t)nx * ny + (size_t)j * nx + i] : Real(0);
+        copies[row * S * w + x] = val;
+        if constexpr (S == 4) copies[(row * S + 2) * w + (w - 1 - x)] = val;
     }
 }
 
 // Tiled transpose through LDS: block (32, 8) handles a 32 x 32 tile of the
-// column copy (32 copy rows i from i0, 32 padded positions p from p0); dst is
-// the image's column copy (slot 1 of its first row), rows 2 W apart.
-template <typename Real>
+// column copies (32 copy rows i from i0, 32 padded positions p from p0); dst
+// is the image's column copy (slot 1 of its first row), rows S W apart; with
+// S = 4 the mirrored column copy (slot 3) is written from the same tile.
+template <typename Real, int S>
 __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real *__restrict__ dst,
                                               int nx, int ny, int nrows, int i0, int p0,
                                               Real (&tile)[32][33]) {
@@ -165,16 +174,20 @@ __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real
     // write: column copy row i, positions p (coalesced along p)
     for (int k = threadIdx.y; k < 32; k += 8) {
         const int i = i0 + k, p = p0 + (int)threadIdx.x;
-        if (i < nrows && p < w) dst[(size_t)i * 2 * w + p] = tile[threadIdx.x][k];
+        if (i < nrows && p < w) {
+            const Real val = tile[threadIdx.x][k];
+            dst[(size_t)i * S * w + p] = val;
+            if constexpr (S == 4) dst[(size_t)i * S * w + 2 * w + (w - 1 - p)] = val;
+        }
     }
     __syncthreads();
 }
 
-// Both padded copies of a batch in one launch of 32 x 8 blocks: the first
+// All padded copies of a batch in one launch of 32 x 8 blocks: the first
 // rows_blocks blocks stride over the row copies, each further block
-// transposes one 32 x 32 tile of one image's column copy (ti x tp tiles per
+// transposes one 32 x 32 tile of one image's column copies (ti x tp tiles per
 // image).
-template <typename Real>
+template <typename Real, int S>
 __global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
                                                   Real *__restrict__ copies, int nx, int ny,
                                                   int nrows, int nb, unsigned rows_blocks, int ti,
@@ -182,15 +195,15 @@ __global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
     __shared__ Real tile[32][33];
     const int tid = threadIdx.y * 32 + threadIdx.x;
     if (blockIdx.x < rows_blocks) {
-        pad_rows_body(img, copies, nx, ny, nrows, nb, (size_t)blockIdx.x * 256 + tid,
-                      (size_t)rows_blocks * 256);
+        pad_rows_body<Real, S>(img, copies, nx, ny, nrows, nb, (size_t)blockIdx.x * 256 + tid,
+                               (size_t)rows_blocks * 256);
         return;
     }
     const int t = (int)(blockIdx.x - rows_blocks);
     const int b = t / (ti * tp), k = t % (ti * tp);
     const int w = padded_width(nx, ny);
-    pad_cols_tile(img + (size_t)b * nx * ny, copies + ((size_t)b * nrows * 2 + 1) * w, nx, ny,
-                  nrows, (k % ti) * 32, (k / ti) * 32, tile);
+    pad_cols_tile<Real, S>(img + (size_t)b * nx * ny, copies + ((size_t)b * nrows * S + 1) * w, nx,
+                           ny, nrows, (k % ti) * 32, (k / ti) * 32, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -215,11 +228,15 @@ struct RayWalk {
     Trap<Real> trap;
     int nq;            // pixels along the cross axis
     int width;         // length of a padded copy's rows (uniform)
-    int lane_off;      // offset of this ray's copy within a row pair: 0 or width
+    // Offsets (values) within a row group of the copies this ray reads: one
+    // read for S = 1 (its own axis' copy, 0 or width); for S = 4, the four
+    // quarter-turn rotations, q = 0, 1 on row r and q = 2, 3 on row nr-1-r
+    // (forward_block).
+    int qoff[4];
     int nr;            // pixels along the march axis
     int r0;            // first row of the walk
     const Real *base;  // the interleaved copies (image 0, row 0), uniform
-    size_t row_stride; // values between rows of a copy (2 width)
+    size_t row_stride; // values between row groups (S width)
     size_t img_stride; // values between images
 };
 
@@ -268,13 +285,15 @@ struct RowStepper<float> {
 
 // Rows rb .. re with windows of T pixels.  Xb is X on row rb for the
 // block's half span, whose s' at frac(X) = 0 is sp_top; hcp is the half blur
-// at padded cross index 0 of row rb.  Sums into blk.
-template <typename Real, int NB, int T, FwdMode MODE>
+// at padded cross index 0 of row rb.  Sums into blk: NB images, and for
+// S = 4 the four rotations of each (accumulator q NB + b).
+template <typename Real, int NB, int T, FwdMode MODE, int S>
 __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Real sp_top,
-                                           Real hcp, int rb, int re, Real (&blk)[NB],
+                                           Real hcp, int rb, int re, Real (&blk)[NB * S],
                                            int &nonzero) {
     constexpr bool kLoad = MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual;
     constexpr bool kFixed = std::is_same<Real, float>::value;
+    static_assert(S == 1 || kLoad, "rotations are read only by the image modes");
     // the window start, clamped so that the window stays inside the padded
     // copy (a clamped window, and the unclamped one it replaces, lie in the
     // zero margin: its s' is then immaterial)
@@ -282,28 +301,33 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
     // s' at the window start is zc (1 - hq - frac(X)); in fixed point frac
     // arrives in units of 2^-32
     const Real zfrac = kFixed ? -w.zcr * Real(2.3283064365386963e-10) : -w.zcr;
-    // row r of both copies starts at one address common to the wave; the
-    // lane's window is a small byte offset from it
+    // row r of every copy starts at one address common to the wave; the
+    // lane's window is a small byte offset from it (S = 4: and row nr-1-r,
+    // walked backwards)
     const Real *rowp = w.base + (size_t)rb * w.row_stride;
+    const Real *mrowp = S == 4 ? w.base + (size_t)(w.nr - 1 - rb) * w.row_stride : rowp;
     RowStepper<Real> X;
     X.start(Xb);
     if constexpr (kFixed) X.anchor(w.dX);
-    for (int r = rb; r <= re; ++r, rowp += w.row_stride) {
+    for (int r = rb; r <= re; ++r, rowp += w.row_stride, mrowp -= w.row_stride) {
         unsigned p;
         Real frac;
         X.row(p_max, p, frac);
         const Real sp0 = fma(zfrac, frac, sp_top);
         const Real hc0 = fma((Real)p, w.dhq, hcp);
         hcp += w.dhr;
-        Real cv[NB][T];
+        Real cv[NB * S][T];
         if constexpr (kLoad) {
-            const Real *pp = reinterpret_cast<const Real *>(
-                reinterpret_cast<const char *>(rowp) +
-                (unsigned)(w.lane_off + (int)p) * (unsigned)sizeof(Real));
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+            for (int q = 0; q < S; ++q) {
+                const Real *pp = reinterpret_cast<const Real *>(
+                    reinterpret_cast<const char *>(q < 2 ? rowp : mrowp) +
+                    (unsigned)(w.qoff[q] + (int)p) * (unsigned)sizeof(Real));
 #pragma unroll
-                for (int t = 0; t < T; ++t) cv[b][t] = pp[b * w.img_stride + t];
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int t = 0; t < T; ++t) cv[q * NB + b][t] = pp[b * w.img_stride + t];
+            }
         } else {
 #pragma unroll
             for (int t = 0; t < T; ++t)
@@ -321,7 +345,7 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
             } else {
                 const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) blk[b] = fma(e, cv[b][t], blk[b]);
+                for (int k = 0; k < NB * S; ++k) blk[k] = fma(e, cv[k][t], blk[k]);
             }
         }
         X.next(w.dX);
@@ -330,11 +354,13 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
 
 // Windows wider than the unrolled variants: same arithmetic, a loop over the
 // window with explicit bounds, X in FP64.
-template <typename Real, int NB, FwdMode MODE>
+template <typename Real, int NB, FwdMode MODE, int S>
 __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp_top, Real hcp,
-                                int rb, int re, Real (&blk)[NB], int &nonzero) {
-    const Real *rowp = w.base + w.lane_off + (size_t)rb * w.row_stride;
-    for (int r = rb; r <= re; ++r, rowp += w.row_stride, X += w.dX, hcp += w.dhr) {
+                                int rb, int re, Real (&blk)[NB * S], int &nonzero) {
+    const Real *rowp = w.base + (size_t)rb * w.row_stride;
+    const Real *mrowp = S == 4 ? w.base + (size_t)(w.nr - 1 - rb) * w.row_stride : rowp;
+    for (int r = rb; r <= re;
+         ++r, rowp += w.row_stride, mrowp -= w.row_stride, X += w.dX, hcp += w.dhr) {
         const double fl = floor(X);
         const int q_lo = (int)fl;
         const Real sp0 = fma(-w.zcr, (Real)(X - fl), sp_top);
@@ -353,8 +379,12 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
                 blk[0] += e;
             } else {
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    blk[b] = fma(e, rowp[kFwdPad + q + b * w.img_stride], blk[b]);
+                for (int k = 0; k < S; ++k) {
+                    const Real *pk = (k < 2 ? rowp : mrowp) + w.qoff[k] + kFwdPad + q;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        blk[k * NB + b] = fma(e, pk[b * w.img_stride], blk[k * NB + b]);
+                }
             }
         }
     }
@@ -364,9 +394,10 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
 // window width is the wave's largest need over the block: the blur grows
 // with depth along the ray, so blocks on the source side take narrower
 // windows than the ray's deepest row would.
-template <typename Real, int NB, FwdMode MODE>
-__device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (&acc)[NB],
+template <typename Real, int NB, FwdMode MODE, int S>
+__device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (&acc)[NB * S],
                                           int &nonzero) {
+    constexpr int K = NB * S;
     for (int rb = w.r0; rb <= r1; rb += kFwdBlockRows) {
         const int re = min(rb + kFwdBlockRows - 1, r1);
         // the block's half span (a lane whose ray misses the block's rows
@@ -380,30 +411,44 @@ __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (
         const Real sp_top = w.zcr * (Real)(1.0 - (double)hqk);
         // half blur at padded cross index 0 of row rb
         const Real hcp = fma(-(Real)kFwdPad, w.dhq, fma((Real)(rb - w.r0), w.dhc, w.hc0));
-        Real blk[NB];
+        Real blk[K];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) blk[b] = 0;
+        for (int k = 0; k < K; ++k) blk[k] = 0;
         switch (Tb) {
             case 1:
-            case 2: walk_block<Real, NB, 2, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
-            case 3: walk_block<Real, NB, 3, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
-            case 4: walk_block<Real, NB, 4, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
-            case 5: walk_block<Real, NB, 5, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
-            case 6: walk_block<Real, NB, 6, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 2: walk_block<Real, NB, 2, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 3: walk_block<Real, NB, 3, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 4: walk_block<Real, NB, 4, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 5: walk_block<Real, NB, 5, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 6: walk_block<Real, NB, 6, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
             case 7:
-            case 8: walk_block<Real, NB, 8, MODE>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 8: walk_block<Real, NB, 8, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
             default:
-                walk_block_wide<Real, NB, MODE>(w, Tb, Xb, sp_top, hcp, rb, re, blk, nonzero);
+                walk_block_wide<Real, NB, MODE, S>(w, Tb, Xb, sp_top, hcp, rb, re, blk, nonzero);
                 break;
         }
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] += blk[b];
+        for (int k = 0; k < K; ++k) acc[k] += blk[k];
     }
 }
 
 // One block of kFwdThreads consecutive rays of view v, starting at cell
 // m_block * kFwdThreads.
-template <typename Real, int NB, FwdMode MODE>
+//
+// S = 4 (square image, views in quarter-turn quadruples v + k nv, k < 4,
+// where G holds the nv views of the first quarter): the entries of view
+// v + k nv on the image c equal those of view v on c rotated by k quarter
+// turns, (c o R^k)(i, j) with R(i, j) = (n-1-j, i), so one walk evaluates
+// every entry once for the four views.  Reading row r of this ray's axis copy
+// (march index r, cross index x), the four rotations sit at
+//   rows:    k = 0 row copy r, x;      1 column copy n-1-r, x;
+//            2 mirrored row copy n-1-r, x;  3 mirrored column copy r, x;
+//   columns: k = 0 column copy r, x;   1 mirrored row copy r, x;
+//            2 mirrored column copy n-1-r, x;  3 row copy n-1-r, x;
+// all at the same padded cross position, so the reads q = 0, 1 share row r
+// and q = 2, 3 row n-1-r.  The outputs are [nb][4][nv][nd]: image b's
+// sinogram of 4 nv views.
+template <typename Real, int NB, FwdMode MODE, int S>
 __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_block,
                                               const Real *__restrict__ copies,
                                               Real *__restrict__ out,
@@ -482,10 +527,22 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     w.nq = nq;
     w.nr = nr;
     w.width = padded_width(G.nx, G.ny);
-    w.row_stride = 2 * (size_t)w.width;
+    w.row_stride = (S == 4 ? 4 : 2) * (size_t)w.width;
     w.img_stride = w.row_stride * (size_t)max(G.nx, G.ny);
     w.base = copies;
-    w.lane_off = by_rows ? 0 : w.width;
+    // copy slots 0 row, 1 column, 2 mirrored row, 3 mirrored column (read q
+    // of rotation k: by rows q = 0, 1, 2, 3 is k = 0, 3, 1, 2; by columns
+    // k = q)
+    if (S == 4) {
+        const int W = w.width;
+        w.qoff[0] = by_rows ? 0 : W;
+        w.qoff[1] = by_rows ? 3 * W : 2 * W;
+        w.qoff[2] = by_rows ? W : 3 * W;
+        w.qoff[3] = by_rows ? 2 * W : 0;
+    } else {
+        w.qoff[0] = by_rows ? 0 : w.width;
+        w.qoff[1] = w.qoff[2] = w.qoff[3] = 0;
+    }
 
     // Support |s'| < hab + hc, with hc bounded by its value at the far side
     // of the disk containing the image.
@@ -531,11 +588,11 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
         w.hqb = (float)(gR * (dq * lc + lm) * fabs(izc) * m);
     }
 
-    Real acc[NB];
+    Real acc[NB * S];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = 0;
+    for (int k = 0; k < NB * S; ++k) acc[k] = 0;
     int nonzero = 0;
-    if (r0 <= r1) walk_rows<Real, NB, MODE>(w, r1, acc, nonzero);
+    if (r0 <= r1) walk_rows<Real, NB, MODE, S>(w, r1, acc, nonzero);
     if (!active) return;
     const Real wbr = tab.wb()[ray];
     if constexpr (MODE == FwdMode::kCount) {
@@ -545,24 +602,34 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
         out[ray] = sum != Real(0) ? Real(1) / sum : Real(0);
     } else {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const Real y = acc[b] * wbr;
-            if constexpr (MODE == FwdMode::kPlain) {
-                out[b * nrays + ray] = y;
-            } else {  // kSirtResidual
-                out[b * nrays + ray] = row_w[ray] * (y_meas[b * nrays + ray] - y);
+        for (int k = 0; k < S; ++k) {
+            // accumulator of rotation k (see above)
+            const int q = S == 1 ? 0 : (by_rows ? (k == 0 ? 0 : k == 1 ? 2 : k == 2 ? 3 : 1) : k);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                Real a = acc[b];
+#pragma unroll
+                for (int qq = 1; qq < S; ++qq)
+                    if (q == qq) a = acc[qq * NB + b];
+                const Real y = a * wbr;
+                const size_t o = (size_t)(b * S + k) * nrays + ray;
+                if constexpr (MODE == FwdMode::kPlain) {
+                    out[o] = y;
+                } else {  // kSirtResidual: row weights of the full view set
+                    out[o] = row_w[(size_t)k * nrays + ray] * (y_meas[o] - y);
+                }
             }
         }
     }
 }
 
-template <typename Real, int NB, FwdMode MODE>
-__global__ __launch_bounds__(kFwdThreads, min_waves(NB, sizeof(Real))) void forward_kernel(
+template <typename Real, int NB, FwdMode MODE, int S>
+__global__ __launch_bounds__(kFwdThreads, min_waves(NB * S, sizeof(Real))) void forward_kernel(
     DevGeom G, const Real *__restrict__ copies,
     Real *__restrict__ out, int *__restrict__ counts, const Real *__restrict__ y_meas,
     const Real *__restrict__ row_w) {
-    forward_block<Real, NB, MODE>(G, blockIdx.y, blockIdx.x, copies, out, counts, y_meas,
-                                  row_w);
+    forward_block<Real, NB, MODE, S>(G, blockIdx.y, blockIdx.x, copies, out, counts, y_meas,
+                                     row_w);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,6 +849,7 @@ __device__ __forceinline__ void back_window_arc(const BackLds<Real, NB, CAP> &l,
 template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
 __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], const DevGeom &G,
                                            int tx, int ty, int group, int groups,
+                                           bool to_partial,
                                            const Real *__restrict__ sino, Real *__restrict__ img,
                                            Real *__restrict__ partial,
                                            const Real *__restrict__ col_w, Real relaxation) {
@@ -927,7 +995,7 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
     for (int p = 0; p < P; ++p) {
         if (!valid[p]) continue;
         const size_t pix = (size_t)(j0 + p * kRowStep) * G.nx + i;
-        if (groups > 1) {
+        if (to_partial) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
                 partial[((size_t)group * NB + b) * npix + pix] = acc[p][b];
@@ -950,12 +1018,12 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
     }
 }
 
+// to_partial: write the per-group sums to `partial` ([group][NB][npix]) even
+// with one group (the quarter-turn form combines them in its own finalize).
 template <typename Real, int NB, int CAP, BackMode MODE, int BEAM>
-__global__ __launch_bounds__(kBackThreads, min_waves(NB, sizeof(Real))) void back_kernel(DevGeom G, const Real *__restrict__ sino,
-                                                            Real *__restrict__ img,
-                                                            Real *__restrict__ partial,
-                                                            const Real *__restrict__ col_w,
-                                                            Real relaxation) {
+__global__ __launch_bounds__(kBackThreads, min_waves(NB, sizeof(Real))) void back_kernel(
+    DevGeom G, const Real *__restrict__ sino, Real *__restrict__ img, Real *__restrict__ partial,
+    const Real *__restrict__ col_w, Real relaxation, int to_partial) {
     __shared__ BackLds<Real, NB, CAP> lds[2];
     // One work-group per (tile, view group), n = tiles x groups of them in a
     // 1-D grid, group-major.  Work-group L runs on XCD L mod kXcds.  With one
@@ -974,7 +1042,8 @@ __global__ __launch_bounds__(kBackThreads, min_waves(NB, sizeof(Real))) void bac
     }
     const int tile = (int)(P % ntiles), group = (int)(P / ntiles);
     back_block<Real, NB, CAP, MODE, BEAM>(lds, G, tile % G.tiles_x, tile / G.tiles_x, group,
-                                          (int)groups, sino, img, partial, col_w, relaxation);
+                                          (int)groups, groups > 1 || to_partial != 0, sino, img,
+                                          partial, col_w, relaxation);
 }
 
 // Sum of the view-group partials in group order, then the back kernel's
@@ -998,6 +1067,59 @@ __global__ __launch_bounds__(256) void back_finalize_kernel(const Real *__restri
             } else {
                 img[b * npix + pix] += relaxation * col_w[pix] * z;
             }
+        }
+    }
+}
+
+// Quarter-turn form of the back projection: the back kernel ran over the
+// first quarter of the views with the sinogram rows of view v + k nv as
+// image k (k < 4) of each input image, so its sum for image k at pixel p is
+// the contribution of views v + k nv at pixel R^k p (R(i, j) = (n-1-j, i);
+// the entries of view v + k nv at R^k p equal those of view v at p).  Pixel
+// (i, j) of the result is therefore
+//   sum_g [P_0(i, j) + P_1(j, n-1-i) + P_2(n-1-i, n-1-j) + P_3(n-1-j, i)],
+// P_k(a, b) the group-g partial of image k at column a, row b.  Block
+// (32, 8) finishes a 32 x 32 tile of image blockIdx.z; the two transposed
+// terms go through LDS so that every global access is coalesced.  Sums are
+// taken in a fixed order (groups inside, rotations outside).
+template <BackMode MODE>
+__global__ __launch_bounds__(256) void back_finalize_quarter_kernel(
+    const float *__restrict__ partial, int groups, int nb4, int n, float *__restrict__ img,
+    const float *__restrict__ col_w, float relaxation) {
+    __shared__ float t1[32][33], t3[32][33];
+    const size_t npix = (size_t)n * n;
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, im = blockIdx.z;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    auto part = [&](int g, int k) { return partial + ((size_t)g * nb4 + im * 4 + k) * npix; };
+    // t1[a][b] = P_1(j0 + b, n-1-i0-a), t3[a][b] = P_3(n-1-j0-b, i0 + a)
+    for (int a = ty; a < 32; a += 8) {
+        const int b = tx;
+        float s1 = 0.0f, s3 = 0.0f;
+        if (i0 + a < n && j0 + b < n) {
+            for (int g = 0; g < groups; ++g) {
+                s1 += part(g, 1)[(size_t)(n - 1 - i0 - a) * n + (j0 + b)];
+                s3 += part(g, 3)[(size_t)(i0 + a) * n + (n - 1 - j0 - b)];
+            }
+        }
+        t1[a][b] = s1;
+        t3[a][b] = s3;
+    }
+    __syncthreads();
+    const int i = i0 + tx;
+    for (int jj = ty; jj < 32; jj += 8) {
+        const int j = j0 + jj;
+        if (i >= n || j >= n) continue;
+        float z0 = 0.0f, z2 = 0.0f;
+        for (int g = 0; g < groups; ++g) {
+            z0 += part(g, 0)[(size_t)j * n + i];
+            z2 += part(g, 2)[(size_t)(n - 1 - j) * n + (n - 1 - i)];
+        }
+        const float z = ((z0 + t1[tx][jj]) + z2) + t3[tx][jj];
+        const size_t pix = (size_t)j * n + i;
+        if constexpr (MODE == BackMode::kPlain) {
+            img[(size_t)im * npix + pix] = z;
+        } else {  // kSirtUpdate
+            img[(size_t)im * npix + pix] += relaxation * col_w[pix] * z;
         }
     }
 }
