@@ -215,6 +215,28 @@ fp_status fp_sirt_step(const fp_geometry *g, float *image,
                        const float *sino_meas, float relaxation, float *work,
                        int32_t batch, void *stream);
 
+/* The SIRT step of fp_sirt_step for callers that cannot allocate device
+ * memory: code under HIP graph capture, serving loops that must not call
+ * hipMalloc, harnesses that forbid it.  Arguments, layouts, result and errors
+ * are those of fp_sirt_step (the same kernels, so the same values), with
+ * three differences:
+ *   - the geometry's SIRT weights must already exist (fp_sirt_prepare or an
+ *     earlier fp_sirt_step built them); otherwise FP_ERR_INVALID_ARG;
+ *   - the launches' scratch (padded image copies, view-group partial sums)
+ *     is a fixed array of FP_NOALLOC_SCRATCH_BYTES in device memory that the
+ *     library holds on every device it runs on until the process ends; the
+ *     batch is processed in chunks that fit it, and a geometry whose single
+ *     image needs more gives FP_ERR_UNSUPPORTED (about 2048 x 2048 images
+ *     and up);
+ *   - the call allocates nothing and waits on nothing on the host, and every
+ *     call on one device shares that array: calls that can overlap on the
+ *     device (different streams, or different host threads without ordering)
+ *     race on it and give wrong results.  Order them on one stream. */
+#define FP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fp_status fp_sirt_step_noalloc(const fp_geometry *g, float *image,
+                               const float *sino_meas, float relaxation, float *work,
+                               int32_t batch, void *stream);
+
 /* Build the SIRT weights R = 1 ./ (A 1) and C = 1 ./ (A^T 1) of a geometry
  * now (fp_sirt_step and fp_sirt_step_multi otherwise build them on first
  * use).  Synchronises `stream` the first time; a no-op afterwards. */

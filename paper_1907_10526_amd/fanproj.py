@@ -65,6 +65,8 @@ _lib.fp_back_reference.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32
 _lib.fp_back_reference.restype = ctypes.c_int
 _lib.fp_sirt_step.argtypes = [_vp, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32, _vp]
 _lib.fp_sirt_step.restype = ctypes.c_int
+_lib.fp_sirt_step_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32, _vp]
+_lib.fp_sirt_step_noalloc.restype = ctypes.c_int
 class FpSirtJob(ctypes.Structure):
     """fp_sirt_job of the C ABI."""
     _fields_ = [("geometry", ctypes.c_void_p), ("image", ctypes.c_void_p),
@@ -86,7 +88,7 @@ _lib.fp_last_error.argtypes = []
 _lib.fp_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ("fp_geometry_create", "fp_geometry_create_desc", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_forward_f64",
-            "fp_back_f64", "fp_forward_reference", "fp_back_reference", "fp_sirt_step",
+            "fp_back_f64", "fp_forward_reference", "fp_back_reference", "fp_sirt_step", "fp_sirt_step_noalloc",
             "fp_sirt_prepare", "fp_sirt_step_multi",
             "fp_count_nonzero", "fp_geometry_device_bytes", "fp_geometry_quarter_turn", "fp_last_error")
 
@@ -196,6 +198,12 @@ def fp_sirt_step(handle, image, sino_meas, relaxation, work, batch, stream=None)
     _check(_lib.fp_sirt_step(handle, _dev_ptr(image, "image"), _dev_ptr(sino_meas, "sino_meas"),
                              float(relaxation), _dev_ptr(work, "work"), int(batch),
                              _stream_handle(stream)))
+
+
+def fp_sirt_step_noalloc(handle, image, sino_meas, relaxation, work, batch, stream=None) -> None:
+    _check(_lib.fp_sirt_step_noalloc(handle, _dev_ptr(image, "image"),
+                                     _dev_ptr(sino_meas, "sino_meas"), float(relaxation),
+                                     _dev_ptr(work, "work"), int(batch), _stream_handle(stream)))
 
 
 def fp_sirt_prepare(handle, stream=None) -> None:
