@@ -25,6 +25,15 @@ sys.path.insert(0, ROOT)
 # square-accumulate FMAs (16), normalisation (reciprocal + multiply) 2,
 # accumulate FMA 2.
 FLOPS_PER_ENTRY = 48
+FLOPS_ACCUMULATE = 2
+
+
+def flops_per_entry(views_per_evaluation: int) -> float:
+    """Algorithmic flops per non-zero entry when one evaluation of the entry
+    (everything but its accumulate FMA) serves `views_per_evaluation` views:
+    4 in the quarter-turn form, where views v + k V/4 share the entries of
+    view v on the quarter-turned image, 1 in the plain form."""
+    return (FLOPS_PER_ENTRY - FLOPS_ACCUMULATE) / views_per_evaluation + FLOPS_ACCUMULATE
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed / dual issue) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
 # The same without packed FP32 instructions (one FP32 FMA per lane per cycle),
@@ -57,11 +66,9 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def batched_pairs(geom, img, nb, steps):
-    """Context beside the batch-1 headline: the same pair on nb images at once
-    (the kernels evaluate each entry once for all images of a batch)."""
+def time_pairs(geom, imgs, steps):
+    """Average milliseconds of one forward + back of `imgs` on `geom`."""
     import torch
-    imgs = torch.stack([torch.roll(img, shifts=3 * b, dims=1) for b in range(nb)])
     sino = geom.forward(imgs)
     back = geom.back(sino)
     stream = torch.cuda.current_stream()
@@ -73,8 +80,61 @@ def batched_pairs(geom, img, nb, steps):
         geom.back(sino, out=back)
     stop.record(stream)
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / steps
-    return {"images": nb, "steps": steps, "ms_per_batch": ms, "pairs_per_s": nb / (ms * 1e-3)}
+    return start.elapsed_time(stop) / steps, sino, back
+
+
+def batched_pairs(geom, img, nb, steps):
+    """Context beside the batch-1 headline: the same pair on nb images at once
+    (the kernels evaluate each entry once for all images of a batch).
+    Returns the record and the last images, sinograms and back projections
+    (the back projection of each image's own forward sinogram)."""
+    import torch
+    imgs = torch.stack([torch.roll(img, shifts=3 * b, dims=1) for b in range(nb)])
+    ms, sino, back = time_pairs(geom, imgs, steps)
+    rec = {"images": nb, "steps": steps, "ms_per_batch": ms, "pairs_per_s": nb / (ms * 1e-3)}
+    return rec, (imgs.cpu().numpy(), sino.cpu().numpy(), back.cpu().numpy())
+
+
+def batch_rel_l2(og, outputs, seed=17):
+    """rel-L2 of a batch's results against the FP64 oracle on sampled rays and
+    pixels of every image (part of the CPU-baseline leg)."""
+    imgs, y, z = outputs
+    nb, nv, nd = y.shape
+    rng = np.random.default_rng(seed)
+    got_f, ref_f, got_b, ref_b = [], [], [], []
+    for b in range(nb):
+        x = imgs[b].astype(np.float64)
+        for _ in range(6):
+            v, m = int(rng.integers(0, nv)), int(rng.integers(nd // 4, 3 * nd // 4))
+            got_f.append(y[b, v, m])
+            ref_f.append(og.forward_ray(x, v, m))
+        yb = y[b].astype(np.float64)
+        for _ in range(2):
+            i, j = int(rng.integers(0, z.shape[2])), int(rng.integers(0, z.shape[1]))
+            got_b.append(z[b, j, i])
+            ref_b.append(og.back_pixel(yb, i, j))
+
+    def rel(a, r):
+        return float(np.linalg.norm(np.subtract(a, r)) / np.linalg.norm(r))
+    return {"forward": rel(got_f, ref_f), "back": rel(got_b, ref_b),
+            "sample": f"{len(got_f)} rays and {len(got_b)} pixels over the {nb} images"}
+
+
+def plain_form_pairs(scan, img, steps):
+    """Context: the same pair with the views listed in reverse order, which
+    the library does not recognise as quarter turns (the plain form, every
+    view evaluated on its own)."""
+    from paper_1907_10526_amd import fanproj
+    kw = scan.kwargs()
+    kw["angles"] = kw["angles"][::-1].copy()
+    g = fanproj.Geometry(**kw)
+    try:
+        assert not g.quarter_turn()
+        ms, _, _ = time_pairs(g, img, steps)
+    finally:
+        g.close()
+    return {"ms_per_pair": ms, "pairs_per_s": 1e3 / ms, "steps": steps,
+            "what": "views in reverse order: every view evaluated on its own"}
 
 
 def parse():
@@ -91,7 +151,8 @@ def parse():
                    help="repeat the oracle sample until this much time has passed (at most 8 passes)")
     p.add_argument("--serve-jobs", type=int, default=1000,
                    help="jobs in the served-vs-plain comparison (0 skips it)")
-    p.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
+    p.add_argument("--serve-rates", type=float, nargs="+", default=[50.0, 30.0],
+                   help="mean arrivals per second of each served-vs-plain trace")
     p.add_argument("--serve-budget-gib", type=float, default=2.0,
                    help="device-memory budget of the serving loop")
     p.add_argument("--serve-step-work", type=float, default=4e9,
@@ -167,27 +228,54 @@ def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample, min_se
 
 def serving(args):
     """Served (continuous batching) vs plain (one job at a time) on the same
-    seeded arrival trace: SIRT jobs of 256/512/1024-pixel images, 180-1440
-    views, 2 x side cells, 20 iterations each."""
+    seeded arrival traces, at each rate of --serve-rates: SIRT jobs of
+    256/512/1024-pixel images, 180-1440 views, 2 x side cells, 20
+    iterations each.  Returns the record and, for the first rate, the final
+    iterates and sinograms of the first two 256 x 256, 180-view jobs (for the
+    oracle check of the CPU-baseline leg)."""
     from paper_1907_10526_amd import serve
-    trace = serve.make_trace(args.serve_jobs, args.serve_rate, seed=5)
-    ex = serve.GpuExecutor()
     budget = int(args.serve_budget_gib * (1 << 30))
-    t0 = time.perf_counter()
-    batched = serve.Server(ex, hbm_budget=budget, step_work=args.serve_step_work).run(trace)
-    print(f"serving: batched loop done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-          flush=True)
-    t0 = time.perf_counter()
-    plain = serve.run_plain(ex, trace)
-    print(f"serving: plain path done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-          flush=True)
-    return {"trace": f"{args.serve_jobs} jobs, Poisson arrivals {args.serve_rate:g}/s (seed 5), "
-                     "image side {256,512,1024}, views {180,360,720,1440}, cells 2 x side, "
-                     "source-centre U[2,4] x side, magnification 1.5, 20 SIRT iterations",
-            "hbm_budget_bytes": budget,
-            "step_work_entries": args.serve_step_work,
-            "batched": serve.latency_stats(batched),
-            "plain": serve.latency_stats(plain)}
+    out = {"trace": f"{args.serve_jobs} jobs, Poisson arrivals (seed 5), image side "
+                    "{256,512,1024}, views {180,360,720,1440}, cells 2 x side, source-centre "
+                    "U[2,4] x side, magnification 1.5, 20 SIRT iterations, sinograms U[0, 4]",
+           "hbm_budget_bytes": budget, "step_work_entries": args.serve_step_work, "rates": {}}
+    kept = None
+    for k, rate in enumerate(args.serve_rates):
+        trace = serve.make_trace(args.serve_jobs, rate, seed=5)
+        check = [s.job_id for s in trace if s.n == 256 and s.n_views == 180][:2] if k == 0 else []
+        ex = serve.GpuExecutor(keep_inputs=set(check))
+        t0 = time.perf_counter()
+        batched = serve.Server(ex, hbm_budget=budget, step_work=args.serve_step_work,
+                               keep_outputs=set(check)).run(trace)
+        print(f"serving {rate:g}/s: batched loop done in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        plain = serve.run_plain(ex, trace)
+        print(f"serving {rate:g}/s: plain path done in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        bs, ps = serve.latency_stats(batched), serve.latency_stats(plain)
+        out["rates"][f"{rate:g}/s"] = {
+            "batched": bs, "plain": ps,
+            "p50_batched_vs_plain": bs["p50_s"] / ps["p50_s"],
+            "p99_batched_vs_plain": bs["p99_s"] / ps["p99_s"]}
+        if check:
+            kept = [(trace[j], ex.inputs[j], batched.outputs[j].cpu().numpy()) for j in check]
+    return out, kept
+
+
+def served_rel_l2(kept):
+    """rel-L2 of served jobs' final iterates against the FP64 oracle's SIRT on
+    the same data (part of the CPU-baseline leg)."""
+    import oracle
+    errs = []
+    for spec, y, x in kept:
+        og = oracle.Geometry(**spec.geometry_kwargs())
+        ref = og.sirt(y.astype(np.float64), spec.iters)
+        errs.append(float(np.linalg.norm(x.astype(np.float64) - ref) / np.linalg.norm(ref)))
+    return {"jobs": [spec.job_id for spec, _, _ in kept], "rel_l2": errs,
+            "worst": max(errs) if errs else None,
+            "what": f"{len(kept)} served 256 x 256, 180-view jobs of the first trace, "
+                    f"{kept[0][0].iters if kept else 0} SIRT iterations"}
 
 
 def main():
@@ -249,7 +337,9 @@ def main():
     step_ms = fwd_ms + bck_ms
     ms_per_step = total_ms / K
 
-    flops = FLOPS_PER_ENTRY * nnz  # per launch (one projection)
+    views_per_eval = 4 if geom.quarter_turn() else 1
+    f_entry = flops_per_entry(views_per_eval)
+    flops = f_entry * nnz  # per launch (one projection)
     kernels = {"forward": float(fwd_ms.mean()), "back": float(bck_ms.mean())}
     dom = max(kernels, key=kernels.get)
     achieved = flops / (kernels[dom] * 1e-3) / 1e12
@@ -261,7 +351,8 @@ def main():
                 "traffic_unit": "bytes per launch", "traffic_profile": TRAFFIC["profile"],
                 "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
                 "flops_per_launch": flops, "entries_per_launch": nnz,
-                "flops_per_entry": FLOPS_PER_ENTRY,
+                "flops_per_entry": f_entry, "views_per_entry_evaluation": views_per_eval,
+                "form": "quarter-turn" if views_per_eval == 4 else "plain",
                 "avg_ms": {k: round(v, 5) for k, v in kernels.items()},
                 "other_kernel_frac": {k: flops / (v * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
                                       for k, v in kernels.items()}}
@@ -290,11 +381,14 @@ def main():
         "roofline": roofline,
     }
 
+    batch_out = None
     if not args.no_batch8:
-        out["batch8"] = batched_pairs(geom, img, 8, max(2, K // 5))
+        out["batch8"], batch_out = batched_pairs(geom, img, 8, max(2, K // 5))
+        out["plain_form"] = plain_form_pairs(scan, img, max(5, K // 2))
 
+    kept = None
     if args.serve_jobs > 0:
-        out["serving"] = serving(args)
+        out["serving"], kept = serving(args)
 
     if not args.no_cpu_baseline:
         k = max(1, min(args.cpu_sample_views, scan.n_views))
@@ -306,6 +400,12 @@ def main():
         rec, rel = cpu_baseline(scan, img_np, sino_in, y_rows, z_part, k, args.cpu_seconds)
         out["cpu_baseline"] = rec
         out["rel_l2_vs_fp64"] = rel
+        if kept:
+            out["serving"]["rel_l2_vs_fp64"] = served_rel_l2(kept)
+        if batch_out is not None:
+            import oracle
+            out["batch8"]["rel_l2_vs_fp64"] = batch_rel_l2(oracle.Geometry(**scan.kwargs()),
+                                                           batch_out)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -147,8 +147,14 @@ typedef struct {
  * accepts a geometry of any beam. */
 fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_geometry **out);
 
-/* Free the geometry's device tables (synchronises the device).  NULL is a
- * no-op.  The geometry must not be in use by queued work. */
+/* Release the geometry.  The call does not wait: its device memory (tables,
+ * SIRT weights) goes to a per-device list of idle blocks that later
+ * geometries reuse only after the work this library queued with it (the
+ * latest launches on every stream that used it) has completed; idle blocks
+ * beyond 1 GiB per device are freed, after that work.  The handle is invalid
+ * on return.  fp_sirt_step_noalloc calls are not tracked: a caller that
+ * destroys a geometry with such calls still queued must synchronise first.
+ * NULL is a no-op. */
 fp_status fp_geometry_destroy(fp_geometry *g);
 
 /* Forward projection y = A c (eq. (6)): for every image of the batch, every
@@ -253,14 +259,18 @@ typedef struct {
 } fp_sirt_job;
 
 /* One SIRT step for each of n_jobs jobs whose geometries (image size, views,
- * detector cells, distances) may all differ.  The padded copies and the
- * forward residuals of up to 12 jobs run as one launch each, every
- * work-group finding its job from the launch's job table; each job's back
- * update then runs as its own launch, split over view groups like
- * fp_sirt_step's.  This is the execution step of continuous batching: a
- * serving loop admits and retires jobs between calls.  The result for each
- * job is that of fp_sirt_step on it alone.  All geometries must live on one
- * device.  n_jobs == 0 is a no-op. */
+ * detector cells, distances) may all differ.  Jobs are grouped by form
+ * (quarter-turn or plain) and beam shape, up to 12 per group; per group the
+ * padded copies and the forward residuals run as one launch each (every
+ * work-group finding its job from the launch's job table), the back
+ * projections as one persistent launch whose work-groups drain the (job,
+ * tile, view group) items of all jobs in turn, and the updates as one more
+ * launch.  (Jobs whose back-projection cell ranges exceed 256 cells per
+ * tile run their own back launches.)  This is the execution step of
+ * continuous batching: a serving loop admits and retires jobs between calls.
+ * The result for each job is that of fp_sirt_step on it alone, to FP32
+ * summation order.  All geometries must live on one device.  n_jobs == 0 is
+ * a no-op. */
 fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs, void *stream);
 
 /* Number of (ray, pixel) pairs with a non-zero entry, counted on the device
@@ -269,6 +279,13 @@ fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs, void *stre
  * to *count on return (the call synchronises `stream`).  Used to price the
  * work of a projection. */
 fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream);
+
+/* Device scratch bytes one fp_sirt_step call on `batch` images of this
+ * geometry takes from the library's reusable per-device buffers (padded
+ * image copies and partial sums; the buffers are shared by all calls and
+ * kept until the process ends).  0 for NULL or batch < 1.  For admission by
+ * free memory. */
+size_t fp_sirt_scratch_bytes(const fp_geometry *g, int32_t batch);
 
 /* Device bytes held by the geometry: its tables and, once built, the FP64
  * tables and the SIRT weights.  0 for NULL.  Serving code uses it for admission by free memory. */

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfanproj.so")
 SOURCES = ["forward.hip", "back_flat_f32.hip", "back_flat_f64.hip", "back_arc_f32.hip", "back_arc_f64.hip",
            "back_parallel_f32.hip", "back_parallel_f64.hip", "back.cpp",
-           "multi.hip", "noalloc.hip", "tables.hip", "reference.hip", "geometry.cpp", "abi.cpp"]
+           "multi.hip", "noalloc.hip", "tables.hip", "reference.hip", "geometry.cpp", "pool.cpp", "abi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

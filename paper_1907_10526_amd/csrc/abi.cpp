@@ -151,10 +151,13 @@ fp_status ensure_weights(fp_geometry *g, hipStream_t stream) {
     if (g->weights_ready) return FP_OK;
     const size_t nr = (size_t)g->nv * g->nd, np = (size_t)g->nx * g->ny;
     hipError_t e = hipSuccess;
-    if (!g->row_w) e = hipMalloc(&g->row_w, nr * sizeof(float));
-    if (e == hipSuccess && !g->col_w) e = hipMalloc(&g->col_w, np * sizeof(float));
+    if (!g->row_w)
+        e = pool_alloc(g->device, nr * sizeof(float), reinterpret_cast<void **>(&g->row_w),
+                       &g->row_cap);
+    if (e == hipSuccess && !g->col_w)
+        e = pool_alloc(g->device, np * sizeof(float), reinterpret_cast<void **>(&g->col_w),
+                       &g->col_cap);
     if (e != hipSuccess) {
-        (void)hipGetLastError();
         set_error(std::string("fp_sirt_step: allocating the SIRT weights failed: ") +
                   hipGetErrorString(e));
         return FP_ERR_OUT_OF_MEMORY;
@@ -173,6 +176,30 @@ fp_status ensure_weights(fp_geometry *g, hipStream_t stream) {
 }
 
 }  // namespace
+
+void note_use(const fp_geometry *gc, hipStream_t s) {
+    fp_geometry *g = const_cast<fp_geometry *>(gc);
+    std::lock_guard<std::mutex> lock(g->use_mu);
+    for (auto &u : g->uses)
+        if (u.first == s) {
+            if (hipEventRecord(u.second, s) != hipSuccess) {
+                (void)hipGetLastError();
+                g->untracked = true;
+            }
+            return;
+        }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        g->untracked = true;
+        return;
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        g->untracked = true;
+    }
+    g->uses.emplace_back(s, ev);
+}
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
@@ -221,6 +248,7 @@ fp_status forward_impl(const fp_geometry *gc, const Real *image, Real *sino, int
                 if (e != hipSuccess) return device_error(fn, e);
                 b0 += nb;
             }
+            note_use(g, s);
             return FP_OK;
         }
     }
@@ -235,6 +263,7 @@ fp_status forward_impl(const fp_geometry *gc, const Real *image, Real *sino, int
         if (e != hipSuccess) return device_error(fn, e);
         b0 += nb;
     }
+    note_use(g, s);
     return FP_OK;
 }
 
@@ -273,6 +302,7 @@ fp_status back_impl(const fp_geometry *gc, const Real *sino, Real *image, int32_
                 if (e != hipSuccess) return device_error(fn, e);
                 b0 += nb;
             }
+            note_use(g, s);
             return FP_OK;
         }
     }
@@ -288,6 +318,7 @@ fp_status back_impl(const fp_geometry *gc, const Real *sino, Real *image, int32_
         if (e != hipSuccess) return device_error(fn, e);
         b0 += nb;
     }
+    note_use(g, s);
     return FP_OK;
 }
 
@@ -333,6 +364,7 @@ fp_status reference_impl(const fp_geometry *g, bool forward, const double *in, d
     const hipError_t e = launch_reference(g, forward, in, out, batch, quad ? quad : 16,
                                           static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_error(fn, e);
+    note_use(g, static_cast<hipStream_t>(stream));
     return FP_OK;
 }
 
@@ -439,8 +471,10 @@ extern "C" fp_status fp_sirt_step(const fp_geometry *g_const, float *image, cons
     Scratch scratch(g->device,
                     std::max<size_t>(sirt_scratch_bytes(g, max_nb, quarter, nullptr), 256), s);
     if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step", scratch.status());
-    return sirt_step_launch(g, image, sino_meas, relaxation, work, batch, max_nb, quarter,
-                            scratch.raw(), s, "fp_sirt_step");
+    st = sirt_step_launch(g, image, sino_meas, relaxation, work, batch, max_nb, quarter,
+                          scratch.raw(), s, "fp_sirt_step");
+    if (st == FP_OK) note_use(g, s);
+    return st;
 }
 
 extern "C" fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void *stream) {
@@ -454,26 +488,25 @@ extern "C" fp_status fp_count_nonzero(const fp_geometry *g, int64_t *count, void
     DeviceGuard guard(g->device);
     if (guard.status() != hipSuccess)
         return device_error("fp_count_nonzero: hipSetDevice", guard.status());
-    const size_t nr = (size_t)g->nv * g->nd;
-    int *d_counts = nullptr;
-    hipError_t e = hipMalloc(&d_counts, nr * sizeof(int));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("fp_count_nonzero: allocation failed");
-        return FP_ERR_OUT_OF_MEMORY;
-    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<int> h(nr);
-    e = launch_forward<float>(g->dev, FwdMode::kCount, 1, nullptr, nullptr, nullptr, d_counts,
-                              nullptr, nullptr, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_counts, nr * sizeof(int), hipMemcpyDeviceToHost, s);
+    const size_t bytes = count_work_bytes(g->dev);
+    Scratch work(g->device, bytes, s);
+    if (work.status() != hipSuccess) return scratch_error("fp_count_nonzero", work.status());
+    unsigned long long total = 0;
+    hipError_t e = launch_count(g->dev, work.raw(), s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, static_cast<char *>(work.raw()) + bytes - sizeof(total),
+                           sizeof(total), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d_counts);
     if (e != hipSuccess) return device_error("fp_count_nonzero", e);
-    int64_t total = 0;
-    for (int c : h) total += c;
-    *count = total;
+    *count = (int64_t)total;
     return FP_OK;
+}
+
+extern "C" size_t fp_sirt_scratch_bytes(const fp_geometry *g, int32_t batch) {
+    if (!g || batch < 1) return 0;
+    const int max_nb = chunk_for(batch, sirt_max_chunk(g, g->quarter));
+    return sirt_scratch_bytes(g, max_nb, g->quarter, nullptr);
 }
 
 extern "C" fp_status fp_sirt_prepare(const fp_geometry *gc, void *stream) {
@@ -488,13 +521,10 @@ extern "C" fp_status fp_sirt_prepare(const fp_geometry *gc, void *stream) {
 
 namespace {
 // Scratch of one job of a grouped step, in the job's form.
-size_t multi_copies_bytes(const fp_geometry *g) {
-    return g->quarter ? forward_quarter_work_bytes(g->dev_quarter, 1)
-                      : forward_work_bytes<float>(g->dev, 1);
-}
-size_t multi_partial_bytes(const fp_geometry *g) {
-    return g->quarter ? back_quarter_work_bytes(g->dev_quarter, 1)
-                      : back_work_bytes<float>(g->dev, 1);
+const DevGeom &multi_geom(const fp_geometry *g) { return g->quarter ? g->dev_quarter : g->dev; }
+size_t multi_job_bytes(const fp_geometry *g) {
+    return (multi_copies_bytes(multi_geom(g)) + 255) / 256 * 256 +
+           (multi_partial_bytes(multi_geom(g), g->quarter) + 255) / 256 * 256;
 }
 }  // namespace
 
@@ -534,48 +564,57 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
         if ((st = check_device_ptr(J.sino_meas, dev, (tag + " sino_meas").c_str())) != FP_OK) return st;
         if ((st = check_device_ptr(J.work, dev, (tag + " work").c_str())) != FP_OK) return st;
         if ((st = ensure_weights(const_cast<fp_geometry *>(J.geometry), s)) != FP_OK) return st;
-        scratch_bytes += (multi_copies_bytes(J.geometry) + 255) / 256 * 256;
-        scratch_bytes += (multi_partial_bytes(J.geometry) + 255) / 256 * 256;
+        scratch_bytes += multi_job_bytes(J.geometry);
     }
     Scratch scratch(dev, scratch_bytes, s);
     if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step_multi", scratch.status());
     char *base = static_cast<char *>(scratch.raw());
     size_t off = 0;
-    // grouped launches of up to kMaxJobsPerLaunch jobs of one form: the
-    // quarter-turn jobs first, then the plain ones (each job's order within
-    // its form kept)
+    // grouped launches of up to kMaxJobsPerLaunch jobs of one form and beam
+    // shape: the quarter-turn jobs first, then the plain ones (each job's
+    // order within its group kept)
     for (int form = 1; form >= 0; --form) {
-        std::vector<int> idx;
-        for (int k = 0; k < n_jobs; ++k)
-            if ((int)jobs[k].geometry->quarter == form) idx.push_back(k);
-        for (size_t k0 = 0; k0 < idx.size(); k0 += kMaxJobsPerLaunch) {
-            MultiArgs args{};
-            args.n = (int)std::min<size_t>(kMaxJobsPerLaunch, idx.size() - k0);
-            args.quarter = form;
-            unsigned fwd = 0;
-            for (int k = 0; k < args.n; ++k) {
-                const fp_sirt_job &J = jobs[idx[k0 + k]];
-                const fp_geometry *g = J.geometry;
-                MultiJob &M = args.job[k];
-                M.g = form ? g->dev_quarter : g->dev;
-                M.copies = reinterpret_cast<float *>(base + off);
-                off += (multi_copies_bytes(g) + 255) / 256 * 256;
-                M.partial = reinterpret_cast<float *>(base + off);
-                off += (multi_partial_bytes(g) + 255) / 256 * 256;
-                M.image = J.image;
-                M.image_out = J.image;
-                M.y_meas = J.sino_meas;
-                M.work = J.work;
-                M.row_w = g->row_w;
-                M.col_w = g->col_w;
-                M.relaxation = J.relaxation;
-                M.fwd_begin = fwd;
-                fwd += (unsigned)M.g.nv * (unsigned)((M.g.nd + kFwdThreads - 1) / kFwdThreads);
+        for (int beam : {FP_FAN_FLAT, FP_FAN_ARC, FP_PARALLEL}) {
+            std::vector<int> idx;
+            for (int k = 0; k < n_jobs; ++k)
+                if ((int)jobs[k].geometry->quarter == form && jobs[k].geometry->beam == beam)
+                    idx.push_back(k);
+            for (size_t k0 = 0; k0 < idx.size(); k0 += kMaxJobsPerLaunch) {
+                MultiArgs args{};
+                args.n = (int)std::min<size_t>(kMaxJobsPerLaunch, idx.size() - k0);
+                args.quarter = form;
+                args.beam = beam;
+                unsigned fwd = 0, items = 0;
+                for (int k = 0; k < args.n; ++k) {
+                    const fp_sirt_job &J = jobs[idx[k0 + k]];
+                    const fp_geometry *g = J.geometry;
+                    MultiJob &M = args.job[k];
+                    M.g = multi_geom(g);
+                    M.copies = reinterpret_cast<float *>(base + off);
+                    M.partial = reinterpret_cast<float *>(
+                        base + off + (multi_copies_bytes(M.g) + 255) / 256 * 256);
+                    off += multi_job_bytes(g);
+                    M.image = J.image;
+                    M.image_out = J.image;
+                    M.y_meas = J.sino_meas;
+                    M.work = J.work;
+                    M.row_w = g->row_w;
+                    M.col_w = g->col_w;
+                    M.relaxation = J.relaxation;
+                    M.fwd_begin = fwd;
+                    const int rays = fwd_rays_per_block(form ? 4 : 1);
+                    fwd += (unsigned)M.g.nv * (unsigned)((M.g.nd + rays - 1) / rays);
+                    M.back_begin = items;
+                    items += (unsigned)(M.g.tiles_x * M.g.tiles_y * M.g.back_groups);
+                    args.cap = std::max(args.cap, M.g.back_cap);
+                }
+                args.fwd_blocks = fwd;
+                args.back_items = items;
+                hipError_t e = launch_sirt_multi(args, s);
+                if (e != hipSuccess) return device_error("fp_sirt_step_multi: launch", e);
             }
-            args.fwd_blocks = fwd;
-            hipError_t e = launch_sirt_multi(args, s);
-            if (e != hipSuccess) return device_error("fp_sirt_step_multi: launch", e);
         }
     }
+    for (int k = 0; k < n_jobs; ++k) note_use(jobs[k].geometry, s);
     return FP_OK;
 }

@@ -77,7 +77,7 @@ hipError_t launch_back_quarter_t(const DevGeom &g, const float *sino, float *img
                            relaxation, 1);
         const int n = g.nx;
         dim3 fgrid((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32), (unsigned)NBI);
-        hipLaunchKernelGGL((back_finalize_quarter_kernel<MODE>), fgrid, dim3(32, 8), 0, stream,
+        hipLaunchKernelGGL((back_finalize_quarter_kernel<MODE>), fgrid, dim3(32, 32), 0, stream,
                            partial, groups, NB, n, img, col_w, relaxation);
         return hipGetLastError();
     }

@@ -31,6 +31,12 @@ __host__ __device__ constexpr int padded_width(int nx, int ny) {
     return (nx > ny ? nx : ny) + 2 * kFwdPad;
 }
 constexpr int kFwdMaxUnrolled = 8;   // widest row window with an unrolled variant
+// Threads per ray of the quarter-turn form's forward (each walks a share of
+// the ray's row blocks; a work-group then covers kFwdThreads / parts rays).
+constexpr int kFwdQuarterParts = 1;
+__host__ __device__ constexpr int fwd_rays_per_block(int rotations) {
+    return kFwdThreads / (rotations == 4 ? kFwdQuarterParts : 1);
+}
 // Batch images processed per launch (the kernels are instantiated for
 // 1, 2, 4 and 8 images sharing one evaluation of every entry).
 constexpr int kMaxBatchChunk = 8;
@@ -189,6 +195,12 @@ hipError_t launch_back_beam(const DevGeom &g, BackMode mode, int nb, const Real 
 template <typename Real>
 int back_max_batch(const DevGeom &g);
 
+// Number of non-zero entries (fp_count_nonzero): the forward's count mode
+// into `work` (count_work_bytes(g) bytes), then one work-group's sum, left
+// as an unsigned 64-bit integer in the last 8 bytes of `work`.
+size_t count_work_bytes(const DevGeom &g);
+hipError_t launch_count(const DevGeom &g, void *work, hipStream_t stream);
+
 // Quarter-turn forms (FP32) for a square image whose views come in
 // quadruples a quarter turn apart (view v + k nv at angle t_v + k pi/2, nv a
 // quarter of the views, k < 4): g describes the first quarter of the views,
@@ -229,22 +241,33 @@ struct MultiJob {
     const float *row_w, *col_w;
     float relaxation;
     unsigned fwd_begin;     // first forward work-group of this job
+    unsigned back_begin;    // first back-projection item (tile, view group) of this job
     float *partial;         // view-group partials of the back update (scratch)
 };
 struct MultiArgs {
     int n;
-    // 1: every job in the quarter-turn form (g = the geometry's dev_quarter,
-    // copies of forward_quarter_work_bytes(g, 1) bytes, partial of
-    // back_quarter_work_bytes(g, 1)); 0: every job in the plain form
+    // 1: every job in the quarter-turn form (g = the geometry's dev_quarter);
+    // 0: every job in the plain form
     int quarter;
+    int beam;               // the beam shape of every job
+    int cap;                // the largest back_cap of the jobs
     unsigned fwd_blocks;
+    unsigned back_items;    // back-projection items of all jobs
     MultiJob job[kMaxJobsPerLaunch];
 };
 static_assert(sizeof(MultiArgs) <= 4000, "kernel arguments must stay under 4 KB");
-// Launch the three phases for args.job[0 .. n) (multi.hip); copies/
-// partial/fwd_begin must be filled in (plain form: copies of
-// forward_work_bytes<float>(g, 1) bytes, partial of back_work_bytes<float>(g, 1)
-// bytes).
+// Scratch of one job of a grouped step (copies, partials).
+size_t multi_copies_bytes(const DevGeom &g);
+size_t multi_partial_bytes(const DevGeom &g, bool quarter);
+// Largest back-projection LDS capacity the grouped back phase takes; jobs
+// with larger cell ranges run their own back launches.
+constexpr int kMultiMaxCap = 256;
+// Launch the phases for args.job[0 .. n) (multi.hip): the padded copies and
+// the forward residuals of all jobs (one launch each), the back
+// projections of all jobs as one persistent launch draining (job, tile,
+// view group) items, and one launch finishing all their updates.
+// copies/partial/fwd_begin/back_begin must be filled in, each job's buffers
+// of multi_copies_bytes and multi_partial_bytes bytes.
 hipError_t launch_sirt_multi(const MultiArgs &args, hipStream_t stream);
 
 }  // namespace fanproj
@@ -262,18 +285,25 @@ struct fp_geometry {
     bool quarter = false;
     fanproj::DevGeom dev_quarter{};
     void *table_block = nullptr;   // one device allocation for the FP32 tables
-    size_t table_bytes = 0;
+    size_t table_bytes = 0, table_cap = 0;   // bytes used, bytes of the block
     // FP64 per-ray tables, built on the first FP64 call.
     std::mutex f64_mu;
     bool f64_ready = false;
     void *f64_block = nullptr;
-    size_t f64_bytes = 0;
+    size_t f64_bytes = 0, f64_cap = 0;
     // SIRT weights R = 1/(A 1) and C = 1/(A^T 1), built on first use.
     std::mutex weights_mu;
     bool weights_ready = false;
     float *row_w = nullptr;        // [nv][nd]
     float *col_w = nullptr;        // [ny][nx]
-    size_t weight_bytes = 0;
+    size_t weight_bytes = 0, row_cap = 0, col_cap = 0;
+    // The streams that launched work on the geometry, each with an event
+    // recorded after its latest launches: fp_geometry_destroy waits for these
+    // (not for the whole device) before freeing the tables.  untracked: an
+    // event could not be created, so destroy waits for the device.
+    std::mutex use_mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+    bool untracked = false;
 };
 
 namespace fanproj {
@@ -325,6 +355,18 @@ hipError_t launch_reference(const fp_geometry *g, bool forward, const double *in
                             int batch, int quad, hipStream_t s);
 // Uploads the FP64 per-ray tables if they are not there yet (thread-safe).
 fp_status ensure_f64_tables(fp_geometry *g);
+// Device memory of geometries (pool.cpp): pool_alloc takes an idle block of
+// a destroyed geometry that fits (waiting for the work queued with it) or
+// allocates one; *capacity receives the block's size, which pool_release
+// needs.  pool_release hands blocks back with the events of the work still
+// queued against them (the pool owns the events from then on); it does not
+// wait.  Device `dev` must be current for both.
+hipError_t pool_alloc(int dev, size_t bytes, void **out, size_t *capacity);
+void pool_release(int dev, const std::vector<std::pair<void *, size_t>> &blocks,
+                  const std::vector<hipEvent_t> &after);
+// Records an event after the work just queued on `s` for the geometry (its
+// device current), for fp_geometry_destroy.
+void note_use(const fp_geometry *g, hipStream_t s);
 // Thread-local error text used by fp_last_error.
 void set_error(const std::string &msg);
 void clear_error();

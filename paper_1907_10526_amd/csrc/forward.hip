@@ -6,12 +6,11 @@
 namespace fanproj {
 namespace {
 
-// S = 1: the plain walk over copies of 2 slots; S = 4: the
-// quarter-turn walk over 4 slots, G holding the first quarter of the views.
+// S = 1: the plain walk; S = 4: the quarter-turn walk, G holding the first
+// quarter of the views.  Both read the same two padded copies.
 template <typename Real, int NB, FwdMode MODE, int S>
 hipError_t launch_fwd_t(const DevGeom &g, const Real *img, Real *work, Real *out, int *counts,
                         const Real *y_meas, const Real *row_w, hipStream_t stream) {
-    constexpr int kSlots = S == 4 ? 4 : 2;
     const Real *copies = nullptr;
     if constexpr (MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual) {
         const int nrows = std::max(g.nx, g.ny);
@@ -19,12 +18,13 @@ hipError_t launch_fwd_t(const DevGeom &g, const Real *img, Real *work, Real *out
         const size_t total = (size_t)NB * nrows * width;
         const unsigned rows_blocks = (unsigned)std::min<size_t>((total + 255) / 256, 4096);
         const int ti = (nrows + 31) / 32, tp = (width + 31) / 32;
-        hipLaunchKernelGGL((pad_kernel<Real, kSlots>), dim3(rows_blocks + (unsigned)(ti * tp * NB)),
+        hipLaunchKernelGGL((pad_kernel<Real>), dim3(rows_blocks + (unsigned)(ti * tp * NB)),
                            dim3(32, 8), 0, stream, img, work, g.nx, g.ny, nrows, NB,
                            rows_blocks, ti, tp);
         copies = work;
     }
-    dim3 grid((g.nd + kFwdThreads - 1) / kFwdThreads, g.nv);
+    constexpr int kRays = fwd_rays_per_block(S);
+    dim3 grid((g.nd + kRays - 1) / kRays, g.nv);
     hipLaunchKernelGGL((forward_kernel<Real, NB, MODE, S>), grid, dim3(kFwdThreads), 0, stream, g,
                        copies, out, counts, y_meas, row_w);
     return hipGetLastError();
@@ -82,9 +82,45 @@ hipError_t launch_forward(const DevGeom &g, FwdMode mode, int nb, const Real *im
     return hipErrorInvalidValue;
 }
 
+namespace {
+// Sum of n per-ray counts by one work-group (integer adds, so the order does
+// not matter), written to *total.
+__global__ __launch_bounds__(1024) void count_sum_kernel(const int *__restrict__ counts, size_t n,
+                                                         unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long part[1024 / 64];
+    unsigned long long s = 0;
+    for (size_t k = threadIdx.x; k < n; k += 1024) s += (unsigned)counts[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 1024 / 64; ++w) t += part[w];
+        *total = t;
+    }
+}
+}  // namespace
+
+size_t count_work_bytes(const DevGeom &g) {
+    return ((size_t)g.nv * g.nd * sizeof(int) + 255) / 256 * 256 + sizeof(unsigned long long);
+}
+
+hipError_t launch_count(const DevGeom &g, void *work, hipStream_t stream) {
+    int *counts = static_cast<int *>(work);
+    auto *total = reinterpret_cast<unsigned long long *>(static_cast<char *>(work) +
+                                                         count_work_bytes(g) -
+                                                         sizeof(unsigned long long));
+    hipError_t e = launch_forward<float>(g, FwdMode::kCount, 1, nullptr, nullptr, nullptr, counts,
+                                         nullptr, nullptr, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_sum_kernel, dim3(1), dim3(1024), 0, stream, counts,
+                       (size_t)g.nv * g.nd, total);
+    return hipGetLastError();
+}
+
 size_t forward_quarter_work_bytes(const DevGeom &g, int nb) {
-    const size_t nrows = (size_t)std::max(g.nx, g.ny);
-    return (size_t)nb * sizeof(float) * nrows * 4 * (size_t)padded_width(g.nx, g.ny);
+    return forward_work_bytes<float>(g, nb);
 }
 
 hipError_t launch_forward_quarter(const DevGeom &g, FwdMode mode, int nb, const float *img,

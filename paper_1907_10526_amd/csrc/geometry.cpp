@@ -49,11 +49,10 @@ fp_status ensure_f64_tables(fp_geometry *g) {
     const size_t nr = (size_t)g->nv * g->nd;
     const size_t per = align_up(nr * sizeof(double), 256);
     const size_t bytes = per * kRayTables;
-    hipError_t e = hipMalloc(&g->f64_block, bytes);
+    hipError_t e = pool_alloc(g->device, bytes, &g->f64_block, &g->f64_cap);
     if (e != hipSuccess) {
         g->f64_block = nullptr;
-        (void)hipGetLastError();
-        set_error("FP64 tables: hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        set_error("FP64 tables: allocating " + std::to_string(bytes) + " bytes failed");
         return FP_ERR_OUT_OF_MEMORY;
     }
     char *base = static_cast<char *>(g->f64_block);
@@ -64,7 +63,7 @@ fp_status ensure_f64_tables(fp_geometry *g) {
     e = launch_ray_tables(g->dev.views, ra, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
-        (void)hipFree(g->f64_block);
+        pool_release(g->device, {{g->f64_block, g->f64_cap}}, {});
         g->f64_block = nullptr;
         return device_error("FP64 tables", e);
     }
@@ -200,17 +199,18 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
     const size_t off_rot64 = off; off = align_up(off + (n_arc ? kBackMaxUnrolled : 0) * sizeof(double2), A);
     const size_t off_max = off; off = align_up(off + 2 * sizeof(int), A);
     g->table_bytes = off;
-    e = hipMalloc(&g->table_block, g->table_bytes);
+    e = pool_alloc(g->device, g->table_bytes, &g->table_block, &g->table_cap);
     if (e != hipSuccess) {
         g->table_block = nullptr;
-        (void)hipGetLastError();
-        set_error("fp_geometry_create: hipMalloc of " + std::to_string(g->table_bytes) +
+        set_error("fp_geometry_create: allocating " + std::to_string(g->table_bytes) +
                   " bytes failed: " + hipGetErrorString(e));
         return FP_ERR_OUT_OF_MEMORY;
     }
     char *base = static_cast<char *>(g->table_block);
     auto fail = [&](const char *what, hipError_t err) {
-        (void)hipFree(g->table_block);
+        (void)hipDeviceSynchronize();   // (the tables' own kernels may be queued)
+        (void)hipGetLastError();
+        pool_release(g->device, {{g->table_block, g->table_cap}}, {});
         g->table_block = nullptr;
         return device_error(what, err);
     };
@@ -266,7 +266,7 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
     for (int cap : kBackCaps)
         if (max_cells + 2 * kBackPad <= cap) { d.back_cap = cap; break; }
     if (d.back_cap == 0 || back_max_batch<float>(d) < 1) {
-        (void)hipFree(g->table_block);
+        pool_release(g->device, {{g->table_block, g->table_cap}}, {});
         g->table_block = nullptr;
         set_error("fp_geometry_create: a back-projection tile spans " + std::to_string(max_cells) +
                   " cells, more than the on-chip staging holds (" + std::to_string(kBackMaxCap) +
@@ -297,16 +297,26 @@ extern "C" fp_status fp_geometry_destroy(fp_geometry *g) {
     int cur = 0;
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess && cur != g->device) e = hipSetDevice(g->device);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    hipError_t f = hipSuccess;
-    if (g->table_block) f = hipFree(g->table_block);
-    if (g->f64_block) (void)hipFree(g->f64_block);
-    if (g->row_w) (void)hipFree(g->row_w);
-    if (g->col_w) (void)hipFree(g->col_w);
+    if (e == hipSuccess) {
+        // The blocks go back to the pool with the events of the work queued
+        // with the geometry (the latest launches on every stream that used
+        // it); nothing waits here.  Without a complete record of that work,
+        // wait for the device instead.
+        std::vector<hipEvent_t> after;
+        {
+            std::lock_guard<std::mutex> lock(g->use_mu);
+            for (auto &u : g->uses) after.push_back(u.second);
+            g->uses.clear();
+            if (g->untracked) e = hipDeviceSynchronize();
+        }
+        pool_release(g->device,
+                     {{g->table_block, g->table_cap}, {g->f64_block, g->f64_cap},
+                      {g->row_w, g->row_cap}, {g->col_w, g->col_cap}},
+                     after);
+    }
     if (cur != g->device) (void)hipSetDevice(cur);
     delete g;
     if (e != hipSuccess) return device_error("fp_geometry_destroy", e);
-    if (f != hipSuccess) return device_error("fp_geometry_destroy: hipFree", f);
     return FP_OK;
 }
 

@@ -101,9 +101,14 @@ __device__ __forceinline__ Real footprint_num(Real sp, Real hc, const Trap<Real>
 }
 
 // Waves per SIMD the projection kernels are compiled for: eight (at most 64
-// VGPRs) for one FP32 image, the occupancy their launches are sized for; no
-// bound for the batched and FP64 variants, which need more registers.
-constexpr int min_waves(int nb, size_t real_bytes) { return nb == 1 && real_bytes == 4 ? 8 : 1; }
+// VGPRs) for one FP32 image, the occupancy their launches are sized for, and
+// for four (the back projection's quarter-turn form, whose 8 waves per SIMD
+// then run in one round: measured 8 % faster than at its natural 5 waves
+// despite a few spilled registers); no bound for the other batched and the
+// FP64 variants, which need more registers.
+constexpr int min_waves(int nb, size_t real_bytes) {
+    return (nb == 1 || nb == 4) && real_bytes == 4 ? 8 : 1;
+}
 
 __device__ __forceinline__ int wave_max(int x) {
 #pragma unroll
@@ -121,22 +126,17 @@ constexpr int kSumBlock = 32;        // views per partial sum of the back projec
 constexpr int kFwdBlockRows = 64;    // rows per block of the forward walk
 
 // ---------------------------------------------------------------------------
-// Padded image copies for the forward walk, each with NR = max(nx, ny) rows of
-// W = NR + 2 pad values (rows and values past the image are zero, so a wave
-// whose rays march along different axes can walk the union of their row
-// ranges with one clamp bound), interleaved row by row: copies [nb][NR][S][W],
-// so that row r of every copy is at one address common to the wave plus a
-// small per-lane offset (a multiple of W):
-//   slot 0, row copy:             pixel (i, j) at (j S + 0) W + pad + i
-//   slot 1, column copy:          pixel (i, j) at (i S + 1) W + pad + j
-// and, with S = 4, the same two of the image mirrored left to right (the
-// quarter-turn rotations of a square image read them, see forward_block):
-//   slot 2, mirrored row copy:    pixel (i, j) at (j S + 2) W + W - 1 - pad - i
-//   slot 3, mirrored column copy: pixel (i, j) at (i S + 3) W + W - 1 - pad - j
+// Padded image copies for the forward walk, row-major and transposed, each
+// with NR = max(nx, ny) rows of W = NR + 2 pad values (rows and values past
+// the image are zero, so a wave whose rays march along different axes can
+// walk the union of their row ranges with one clamp bound), interleaved row
+// by row: copies [nb][NR][2][W], so that row r of either copy is at one
+// address common to the wave plus a small per-lane offset (0 or W):
+//   row copy  (slot 0): pixel (i, j) at (j * 2 + 0) * W + pad + i
+//   col copy  (slot 1): pixel (i, j) at (i * 2 + 1) * W + pad + j
 // ---------------------------------------------------------------------------
-// Row copies (slots 0 and 2) of images [0, nb): work item e of the flattened
-// row copy.
-template <typename Real, int S>
+// Row copy (slot 0) of images [0, nb): work item e of the flattened copy.
+template <typename Real>
 __device__ __forceinline__ void pad_rows_body(const Real *__restrict__ img,
                                               Real *__restrict__ copies, int nx, int ny,
                                               int nrows, int nb, size_t first, size_t stride) {
@@ -144,21 +144,17 @@ __device__ __forceinline__ void pad_rows_body(const Real *__restrict__ img,
     const size_t total = (size_t)w * nrows * nb;
     for (size_t e = first; e < total; e += stride) {
         const size_t row = e / w;    // b * nrows + j
-        const int x = (int)(e % w);
-        const int j = (int)(row % nrows), i = x - kFwdPad;
+        const int j = (int)(row % nrows), i = (int)(e % w) - kFwdPad;
         const size_t b = row / nrows;
-        const Real val =
+        copies[row * 2 * w + e % w] =
             (i >= 0 && i < nx && j < ny) ? img[b * (size_t)nx * ny + (size_t)j * nx + i] : Real(0);
-        copies[row * S * w + x] = val;
-        if constexpr (S == 4) copies[(row * S + 2) * w + (w - 1 - x)] = val;
     }
 }
 
 // Tiled transpose through LDS: block (32, 8) handles a 32 x 32 tile of the
-// column copies (32 copy rows i from i0, 32 padded positions p from p0); dst
-// is the image's column copy (slot 1 of its first row), rows S W apart; with
-// S = 4 the mirrored column copy (slot 3) is written from the same tile.
-template <typename Real, int S>
+// column copy (32 copy rows i from i0, 32 padded positions p from p0); dst is
+// the image's column copy (slot 1 of its first row), rows 2 W apart.
+template <typename Real>
 __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real *__restrict__ dst,
                                               int nx, int ny, int nrows, int i0, int p0,
                                               Real (&tile)[32][33]) {
@@ -174,20 +170,16 @@ __device__ __forceinline__ void pad_cols_tile(const Real *__restrict__ src, Real
     // write: column copy row i, positions p (coalesced along p)
     for (int k = threadIdx.y; k < 32; k += 8) {
         const int i = i0 + k, p = p0 + (int)threadIdx.x;
-        if (i < nrows && p < w) {
-            const Real val = tile[threadIdx.x][k];
-            dst[(size_t)i * S * w + p] = val;
-            if constexpr (S == 4) dst[(size_t)i * S * w + 2 * w + (w - 1 - p)] = val;
-        }
+        if (i < nrows && p < w) dst[(size_t)i * 2 * w + p] = tile[threadIdx.x][k];
     }
     __syncthreads();
 }
 
-// All padded copies of a batch in one launch of 32 x 8 blocks: the first
+// Both padded copies of a batch in one launch of 32 x 8 blocks: the first
 // rows_blocks blocks stride over the row copies, each further block
-// transposes one 32 x 32 tile of one image's column copies (ti x tp tiles per
+// transposes one 32 x 32 tile of one image's column copy (ti x tp tiles per
 // image).
-template <typename Real, int S>
+template <typename Real>
 __global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
                                                   Real *__restrict__ copies, int nx, int ny,
                                                   int nrows, int nb, unsigned rows_blocks, int ti,
@@ -195,15 +187,15 @@ __global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
     __shared__ Real tile[32][33];
     const int tid = threadIdx.y * 32 + threadIdx.x;
     if (blockIdx.x < rows_blocks) {
-        pad_rows_body<Real, S>(img, copies, nx, ny, nrows, nb, (size_t)blockIdx.x * 256 + tid,
-                               (size_t)rows_blocks * 256);
+        pad_rows_body(img, copies, nx, ny, nrows, nb, (size_t)blockIdx.x * 256 + tid,
+                      (size_t)rows_blocks * 256);
         return;
     }
     const int t = (int)(blockIdx.x - rows_blocks);
     const int b = t / (ti * tp), k = t % (ti * tp);
     const int w = padded_width(nx, ny);
-    pad_cols_tile<Real, S>(img + (size_t)b * nx * ny, copies + ((size_t)b * nrows * S + 1) * w, nx,
-                           ny, nrows, (k % ti) * 32, (k / ti) * 32, tile);
+    pad_cols_tile(img + (size_t)b * nx * ny, copies + ((size_t)b * nrows * 2 + 1) * w, nx, ny,
+                  nrows, (k % ti) * 32, (k / ti) * 32, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -228,15 +220,16 @@ struct RayWalk {
     Trap<Real> trap;
     int nq;            // pixels along the cross axis
     int width;         // length of a padded copy's rows (uniform)
-    // Offsets (values) within a row group of the copies this ray reads: one
+    // Offsets (values) within a row pair of the copies this ray reads: one
     // read for S = 1 (its own axis' copy, 0 or width); for S = 4, the four
-    // quarter-turn rotations, q = 0, 1 on row r and q = 2, 3 on row nr-1-r
-    // (forward_block).
+    // quarter-turn rotations (forward_block): q = 0 its own copy on row r,
+    // q = 1 the other copy on row r read mirrored, q = 2 the other copy on
+    // row nr-1-r, q = 3 its own copy on row nr-1-r read mirrored.
     int qoff[4];
     int nr;            // pixels along the march axis
     int r0;            // first row of the walk
     const Real *base;  // the interleaved copies (image 0, row 0), uniform
-    size_t row_stride; // values between row groups (S width)
+    size_t row_stride; // values between row pairs (2 width)
     size_t img_stride; // values between images
 };
 
@@ -291,6 +284,7 @@ template <typename Real, int NB, int T, FwdMode MODE, int S>
 __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Real sp_top,
                                            Real hcp, int rb, int re, Real (&blk)[NB * S],
                                            int &nonzero) {
+    constexpr int K = NB * S;
     constexpr bool kLoad = MODE == FwdMode::kPlain || MODE == FwdMode::kSirtResidual;
     constexpr bool kFixed = std::is_same<Real, float>::value;
     static_assert(S == 1 || kLoad, "rotations are read only by the image modes");
@@ -304,29 +298,27 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
     // row r of every copy starts at one address common to the wave; the
     // lane's window is a small byte offset from it (S = 4: and row nr-1-r,
     // walked backwards)
-    const Real *rowp = w.base + (size_t)rb * w.row_stride;
-    const Real *mrowp = S == 4 ? w.base + (size_t)(w.nr - 1 - rb) * w.row_stride : rowp;
-    RowStepper<Real> X;
-    X.start(Xb);
-    if constexpr (kFixed) X.anchor(w.dX);
-    for (int r = rb; r <= re; ++r, rowp += w.row_stride, mrowp -= w.row_stride) {
-        unsigned p;
-        Real frac;
-        X.row(p_max, p, frac);
-        const Real sp0 = fma(zfrac, frac, sp_top);
-        const Real hc0 = fma((Real)p, w.dhq, hcp);
-        hcp += w.dhr;
-        Real cv[NB * S][T];
+    const size_t stride = w.row_stride;
+    const Real *rowp = w.base + (size_t)rb * stride;
+    const Real *mrowp = S == 4 ? w.base + (size_t)(w.nr - 1 - rb) * stride : rowp;
+
+    // the window's pixel values of row r (rows rp and mp) starting at p
+    auto load = [&](Real (&cv)[K][T], const Real *rp, const Real *mp, unsigned p, int r) {
         if constexpr (kLoad) {
 #pragma unroll
             for (int q = 0; q < S; ++q) {
+                // reads q = 1, 3 run backwards from the mirrored position
+                // W - 1 - p (negative immediate offsets)
+                const bool mir = q & 1;
                 const Real *pp = reinterpret_cast<const Real *>(
-                    reinterpret_cast<const char *>(q < 2 ? rowp : mrowp) +
-                    (unsigned)(w.qoff[q] + (int)p) * (unsigned)sizeof(Real));
+                    reinterpret_cast<const char *>(q < 2 ? rp : mp) +
+                    (unsigned)(w.qoff[q] + (mir ? w.width - 1 - (int)p : (int)p)) *
+                        (unsigned)sizeof(Real));
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
-                    for (int t = 0; t < T; ++t) cv[q * NB + b][t] = pp[b * w.img_stride + t];
+                    for (int t = 0; t < T; ++t)
+                        cv[q * NB + b][t] = pp[b * w.img_stride + (mir ? -t : t)];
             }
         } else {
 #pragma unroll
@@ -334,6 +326,12 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
                 cv[0][t] = ((unsigned)((int)p - kFwdPad + t) < (unsigned)w.nq && r < w.nr)
                                ? Real(1) : Real(0);
         }
+    };
+    // the entries of one row (window at p, fraction frac, half blur hcr at
+    // padded cross index 0)
+    auto entries = [&](const Real (&cv)[K][T], unsigned p, Real frac, Real hcr) {
+        const Real sp0 = fma(zfrac, frac, sp_top);
+        const Real hc0 = fma((Real)p, w.dhq, hcr);
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             // (t == 0 spelled out: an FMA by zero does not fold)
@@ -345,10 +343,25 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
             } else {
                 const Real e = footprint_num(sp, hc, w.trap) * fast_rcp(hc);
 #pragma unroll
-                for (int k = 0; k < NB * S; ++k) blk[k] = fma(e, cv[k][t], blk[k]);
+                for (int k = 0; k < K; ++k) blk[k] = fma(e, cv[k][t], blk[k]);
             }
         }
+    };
+
+    RowStepper<Real> X;
+    X.start(Xb);
+    if constexpr (kFixed) X.anchor(w.dX);
+    for (int r = rb; r <= re; ++r) {
+        unsigned p;
+        Real frac;
+        X.row(p_max, p, frac);
+        Real cv[K][T];
+        load(cv, rowp, mrowp, p, r);
+        entries(cv, p, frac, hcp);
+        hcp += w.dhr;
         X.next(w.dX);
+        rowp += stride;
+        if constexpr (S == 4) mrowp -= stride;
     }
 }
 
@@ -360,7 +373,7 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
     const Real *rowp = w.base + (size_t)rb * w.row_stride;
     const Real *mrowp = S == 4 ? w.base + (size_t)(w.nr - 1 - rb) * w.row_stride : rowp;
     for (int r = rb; r <= re;
-         ++r, rowp += w.row_stride, mrowp -= w.row_stride, X += w.dX, hcp += w.dhr) {
+         ++r, rowp += w.row_stride, mrowp -= S == 4 ? w.row_stride : 0, X += w.dX, hcp += w.dhr) {
         const double fl = floor(X);
         const int q_lo = (int)fl;
         const Real sp0 = fma(-w.zcr, (Real)(X - fl), sp_top);
@@ -380,7 +393,10 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
             } else {
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
-                    const Real *pk = (k < 2 ? rowp : mrowp) + w.qoff[k] + kFwdPad + q;
+                    // (reads k = 1, 3 mirrored, as in walk_block)
+                    const int x = kFwdPad + q;
+                    const Real *pk =
+                        (k < 2 ? rowp : mrowp) + w.qoff[k] + ((k & 1) ? w.width - 1 - x : x);
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
                         blk[k * NB + b] = fma(e, pk[b * w.img_stride], blk[k * NB + b]);
@@ -395,10 +411,10 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
 // with depth along the ray, so blocks on the source side take narrower
 // windows than the ray's deepest row would.
 template <typename Real, int NB, FwdMode MODE, int S>
-__device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (&acc)[NB * S],
-                                          int &nonzero) {
+__device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r_first, int r1,
+                                          Real (&acc)[NB * S], int &nonzero) {
     constexpr int K = NB * S;
-    for (int rb = w.r0; rb <= r1; rb += kFwdBlockRows) {
+    for (int rb = r_first; rb <= r1; rb += kFwdBlockRows) {
         const int re = min(rb + kFwdBlockRows - 1, r1);
         // the block's half span (a lane whose ray misses the block's rows
         // reads only the zero margin, whatever its window)
@@ -422,7 +438,15 @@ __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (
             case 5: walk_block<Real, NB, 5, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
             case 6: walk_block<Real, NB, 6, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
             case 7:
-            case 8: walk_block<Real, NB, 8, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            case 8:
+                // (the quarter-turn form holds four loads per pixel: its
+                // widest unrolled window is 6, which keeps its registers
+                // for more waves)
+                if constexpr (S == 1) {
+                    walk_block<Real, NB, 8, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero);
+                    break;
+                }
+                [[fallthrough]];
             default:
                 walk_block_wide<Real, NB, MODE, S>(w, Tb, Xb, sp_top, hcp, rb, re, blk, nonzero);
                 break;
@@ -432,22 +456,23 @@ __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r1, Real (
     }
 }
 
-// One block of kFwdThreads consecutive rays of view v, starting at cell
-// m_block * kFwdThreads.
+// One work-group of fwd_rays_per_block(S) consecutive rays of view v,
+// starting at cell m_block times that.
 //
 // S = 4 (square image, views in quarter-turn quadruples v + k nv, k < 4,
 // where G holds the nv views of the first quarter): the entries of view
 // v + k nv on the image c equal those of view v on c rotated by k quarter
 // turns, (c o R^k)(i, j) with R(i, j) = (n-1-j, i), so one walk evaluates
-// every entry once for the four views.  Reading row r of this ray's axis copy
-// (march index r, cross index x), the four rotations sit at
-//   rows:    k = 0 row copy r, x;      1 column copy n-1-r, x;
-//            2 mirrored row copy n-1-r, x;  3 mirrored column copy r, x;
-//   columns: k = 0 column copy r, x;   1 mirrored row copy r, x;
-//            2 mirrored column copy n-1-r, x;  3 row copy n-1-r, x;
-// all at the same padded cross position, so the reads q = 0, 1 share row r
-// and q = 2, 3 row n-1-r.  The outputs are [nb][4][nv][nd]: image b's
-// sinogram of 4 nv views.
+// every entry once for the four views.  Walking row r of its own axis' copy
+// at cross position x, a ray finds the four rotations at
+//   k = 0: its own copy, row r, x
+//   rows:    k = 1 column copy, row n-1-r, x;  2 row copy, row n-1-r, mirrored x;
+//            k = 3 column copy, row r, mirrored x
+//   columns: k = 1 row copy, row r, mirrored x;  2 column copy, row n-1-r,
+//            mirrored x;  k = 3 row copy, row n-1-r, x
+// (mirrored x = W - 1 - x, a read running backwards), so the reads q = 0, 1
+// share row r and q = 2, 3 row n-1-r (RayWalk::qoff).  The outputs are
+// [nb][4][nv][nd]: image b's sinogram of 4 nv views.
 template <typename Real, int NB, FwdMode MODE, int S>
 __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_block,
                                               const Real *__restrict__ copies,
@@ -456,7 +481,13 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
                                               const Real *__restrict__ y_meas,
                                               const Real *__restrict__ row_w) {
     const RayTables<Real> &tab = ray_tables<Real>(G);
-    const int m_thread = m_block * kFwdThreads + threadIdx.x;
+    // S = 4: the work-group's two halves walk the first and the second half
+    // of the row blocks of the same rays (waves w and w + 2 hold the same
+    // rays, so their row ranges agree)
+    constexpr int kParts = S == 4 ? kFwdQuarterParts : 1;
+    constexpr int kRays = kFwdThreads / kParts;
+    const int part = (int)threadIdx.x / kRays;
+    const int m_thread = m_block * kRays + (int)threadIdx.x % kRays;
     const bool active = m_thread < G.nd;
     // threads past the last cell walk the last ray (their wave needs them for
     // the wave-wide reductions) and write nothing
@@ -527,21 +558,18 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     w.nq = nq;
     w.nr = nr;
     w.width = padded_width(G.nx, G.ny);
-    w.row_stride = (S == 4 ? 4 : 2) * (size_t)w.width;
+    w.row_stride = 2 * (size_t)w.width;
     w.img_stride = w.row_stride * (size_t)max(G.nx, G.ny);
     w.base = copies;
-    // copy slots 0 row, 1 column, 2 mirrored row, 3 mirrored column (read q
-    // of rotation k: by rows q = 0, 1, 2, 3 is k = 0, 3, 1, 2; by columns
-    // k = q)
-    if (S == 4) {
-        const int W = w.width;
-        w.qoff[0] = by_rows ? 0 : W;
-        w.qoff[1] = by_rows ? 3 * W : 2 * W;
-        w.qoff[2] = by_rows ? W : 3 * W;
-        w.qoff[3] = by_rows ? 2 * W : 0;
-    } else {
-        w.qoff[0] = by_rows ? 0 : w.width;
-        w.qoff[1] = w.qoff[2] = w.qoff[3] = 0;
+    // own copy: slot 0 (rows) or 1 (columns); the other copy the other slot
+    // (read q of rotation k: by rows q = 0, 1, 2, 3 is k = 0, 3, 1, 2; by
+    // columns k = 0, 1, 3, 2)
+    {
+        const int own = by_rows ? 0 : w.width, other = by_rows ? w.width : 0;
+        w.qoff[0] = own;
+        w.qoff[1] = other;
+        w.qoff[2] = other;
+        w.qoff[3] = own;
     }
 
     // Support |s'| < hab + hc, with hc bounded by its value at the far side
@@ -592,7 +620,29 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 #pragma unroll
     for (int k = 0; k < NB * S; ++k) acc[k] = 0;
     int nonzero = 0;
-    if (r0 <= r1) walk_rows<Real, NB, MODE, S>(w, r1, acc, nonzero);
+    if constexpr (kParts == 1) {
+        if (r0 <= r1) walk_rows<Real, NB, MODE, S>(w, r0, r1, acc, nonzero);
+    } else {
+        if (r0 <= r1) {
+            const int blocks = (r1 - r0) / kFwdBlockRows + 1;
+            const int r_mid = r0 + (blocks + 1) / 2 * kFwdBlockRows;   // first row of part 1
+            if (part == 0)
+                walk_rows<Real, NB, MODE, S>(w, r0, min(r1, r_mid - 1), acc, nonzero);
+            else if (r_mid <= r1)
+                walk_rows<Real, NB, MODE, S>(w, r_mid, r1, acc, nonzero);
+        }
+        // part 1 hands its sums to part 0 through LDS (fixed order: part 0's
+        // rows first)
+        __shared__ Real part_acc[NB * S][kRays];
+        if (part == 1) {
+#pragma unroll
+            for (int k = 0; k < NB * S; ++k) part_acc[k][threadIdx.x - kRays] = acc[k];
+        }
+        __syncthreads();
+        if (part == 1) return;
+#pragma unroll
+        for (int k = 0; k < NB * S; ++k) acc[k] += part_acc[k][threadIdx.x];
+    }
     if (!active) return;
     const Real wbr = tab.wb()[ray];
     if constexpr (MODE == FwdMode::kCount) {
@@ -604,7 +654,8 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             // accumulator of rotation k (see above)
-            const int q = S == 1 ? 0 : (by_rows ? (k == 0 ? 0 : k == 1 ? 2 : k == 2 ? 3 : 1) : k);
+            const int q = S == 1 ? 0
+                                 : (k == 0 ? 0 : k == 2 ? 3 : (k == 1) == by_rows ? 2 : 1);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 Real a = acc[b];
@@ -624,7 +675,7 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 }
 
 template <typename Real, int NB, FwdMode MODE, int S>
-__global__ __launch_bounds__(kFwdThreads, min_waves(NB * S, sizeof(Real))) void forward_kernel(
+__global__ __launch_bounds__(kFwdThreads, S == 1 ? min_waves(NB, sizeof(Real)) : 1) void forward_kernel(
     DevGeom G, const Real *__restrict__ copies,
     Real *__restrict__ out, int *__restrict__ counts, const Real *__restrict__ y_meas,
     const Real *__restrict__ row_w) {
@@ -1079,49 +1130,56 @@ __global__ __launch_bounds__(256) void back_finalize_kernel(const Real *__restri
 // (i, j) of the result is therefore
 //   sum_g [P_0(i, j) + P_1(j, n-1-i) + P_2(n-1-i, n-1-j) + P_3(n-1-j, i)],
 // P_k(a, b) the group-g partial of image k at column a, row b.  Block
-// (32, 8) finishes a 32 x 32 tile of image blockIdx.z; the two transposed
-// terms go through LDS so that every global access is coalesced.  Sums are
-// taken in a fixed order (groups inside, rotations outside).
+// (32, 32) finishes a 32 x 32 tile of image blockIdx.z, one pixel per
+// thread; the two transposed terms go through LDS so that every global
+// access is coalesced.  Sums are taken in a fixed order (groups inside,
+// rotations outside).
 template <BackMode MODE>
-__global__ __launch_bounds__(256) void back_finalize_quarter_kernel(
-    const float *__restrict__ partial, int groups, int nb4, int n, float *__restrict__ img,
-    const float *__restrict__ col_w, float relaxation) {
+__device__ __forceinline__ void finalize_quarter_tile(const float *__restrict__ partial,
+                                                      int groups, int nb4, int n, int im, int i0,
+                                                      int j0, float *__restrict__ img,
+                                                      const float *__restrict__ col_w,
+                                                      float relaxation) {
     __shared__ float t1[32][33], t3[32][33];
     const size_t npix = (size_t)n * n;
-    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, im = blockIdx.z;
     const int tx = threadIdx.x, ty = threadIdx.y;
     auto part = [&](int g, int k) { return partial + ((size_t)g * nb4 + im * 4 + k) * npix; };
-    // t1[a][b] = P_1(j0 + b, n-1-i0-a), t3[a][b] = P_3(n-1-j0-b, i0 + a)
-    for (int a = ty; a < 32; a += 8) {
-        const int b = tx;
+    // t1[a][b] = P_1(j0 + b, n-1-i0-a), t3[a][b] = P_3(n-1-j0-b, i0 + a), with
+    // a = ty, b = tx (reads along b)
+    {
         float s1 = 0.0f, s3 = 0.0f;
-        if (i0 + a < n && j0 + b < n) {
+        if (i0 + ty < n && j0 + tx < n) {
             for (int g = 0; g < groups; ++g) {
-                s1 += part(g, 1)[(size_t)(n - 1 - i0 - a) * n + (j0 + b)];
-                s3 += part(g, 3)[(size_t)(i0 + a) * n + (n - 1 - j0 - b)];
+                s1 += part(g, 1)[(size_t)(n - 1 - i0 - ty) * n + (j0 + tx)];
+                s3 += part(g, 3)[(size_t)(i0 + ty) * n + (n - 1 - j0 - tx)];
             }
         }
-        t1[a][b] = s1;
-        t3[a][b] = s3;
+        t1[ty][tx] = s1;
+        t3[ty][tx] = s3;
     }
     __syncthreads();
-    const int i = i0 + tx;
-    for (int jj = ty; jj < 32; jj += 8) {
-        const int j = j0 + jj;
-        if (i >= n || j >= n) continue;
-        float z0 = 0.0f, z2 = 0.0f;
-        for (int g = 0; g < groups; ++g) {
-            z0 += part(g, 0)[(size_t)j * n + i];
-            z2 += part(g, 2)[(size_t)(n - 1 - j) * n + (n - 1 - i)];
-        }
-        const float z = ((z0 + t1[tx][jj]) + z2) + t3[tx][jj];
-        const size_t pix = (size_t)j * n + i;
-        if constexpr (MODE == BackMode::kPlain) {
-            img[(size_t)im * npix + pix] = z;
-        } else {  // kSirtUpdate
-            img[(size_t)im * npix + pix] += relaxation * col_w[pix] * z;
-        }
+    const int i = i0 + tx, j = j0 + ty;
+    if (i >= n || j >= n) return;
+    float z0 = 0.0f, z2 = 0.0f;
+    for (int g = 0; g < groups; ++g) {
+        z0 += part(g, 0)[(size_t)j * n + i];
+        z2 += part(g, 2)[(size_t)(n - 1 - j) * n + (n - 1 - i)];
     }
+    const float z = ((z0 + t1[tx][ty]) + z2) + t3[tx][ty];
+    const size_t pix = (size_t)j * n + i;
+    if constexpr (MODE == BackMode::kPlain) {
+        img[(size_t)im * npix + pix] = z;
+    } else {  // kSirtUpdate
+        img[(size_t)im * npix + pix] += relaxation * col_w[pix] * z;
+    }
+}
+
+template <BackMode MODE>
+__global__ __launch_bounds__(1024) void back_finalize_quarter_kernel(
+    const float *__restrict__ partial, int groups, int nb4, int n, float *__restrict__ img,
+    const float *__restrict__ col_w, float relaxation) {
+    finalize_quarter_tile<MODE>(partial, groups, nb4, n, blockIdx.z, blockIdx.x * 32,
+                                blockIdx.y * 32, img, col_w, relaxation);
 }
 
 }  // namespace

@@ -82,6 +82,8 @@ _lib.fp_count_nonzero.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp]
 _lib.fp_count_nonzero.restype = ctypes.c_int
 _lib.fp_geometry_device_bytes.argtypes = [_vp]
 _lib.fp_geometry_device_bytes.restype = ctypes.c_size_t
+_lib.fp_sirt_scratch_bytes.argtypes = [_vp, ctypes.c_int32]
+_lib.fp_sirt_scratch_bytes.restype = ctypes.c_size_t
 _lib.fp_geometry_quarter_turn.argtypes = [_vp]
 _lib.fp_geometry_quarter_turn.restype = ctypes.c_int32
 _lib.fp_last_error.argtypes = []
@@ -90,7 +92,8 @@ _lib.fp_last_error.restype = ctypes.c_char_p
 EXPORTED = ("fp_geometry_create", "fp_geometry_create_desc", "fp_geometry_destroy", "fp_forward", "fp_back", "fp_forward_f64",
             "fp_back_f64", "fp_forward_reference", "fp_back_reference", "fp_sirt_step", "fp_sirt_step_noalloc",
             "fp_sirt_prepare", "fp_sirt_step_multi",
-            "fp_count_nonzero", "fp_geometry_device_bytes", "fp_geometry_quarter_turn", "fp_last_error")
+            "fp_count_nonzero", "fp_sirt_scratch_bytes", "fp_geometry_device_bytes", "fp_geometry_quarter_turn",
+            "fp_last_error")
 
 
 class FanprojError(RuntimeError):
@@ -230,6 +233,10 @@ def fp_geometry_device_bytes(handle) -> int:
     return int(_lib.fp_geometry_device_bytes(handle))
 
 
+def fp_sirt_scratch_bytes(handle, batch=1) -> int:
+    return int(_lib.fp_sirt_scratch_bytes(handle, int(batch)))
+
+
 def fp_geometry_quarter_turn(handle) -> bool:
     return bool(_lib.fp_geometry_quarter_turn(handle))
 
@@ -336,6 +343,9 @@ class Geometry:
 
     def device_bytes(self) -> int:
         return fp_geometry_device_bytes(self.handle)
+
+    def sirt_scratch_bytes(self, batch=1) -> int:
+        return fp_sirt_scratch_bytes(self.handle, batch)
 
     def quarter_turn(self) -> bool:
         """Whether FP32 projections run in the quarter-turn form."""

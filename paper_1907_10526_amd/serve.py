@@ -86,18 +86,44 @@ def job_iteration_work(spec: JobSpec) -> float:
     return 2.0 * 3.0 * spec.n * spec.n * spec.n_views
 
 
-def job_device_bytes(spec: JobSpec) -> int:
+def _view_groups(tiles: int, views: int, cus: int) -> int:
+    """View groups the library's back projection splits `views` into over
+    `tiles` tiles (about 8 work-groups per compute unit, at most 32, at
+    least 8 views per group)."""
+    g = max(1, min(-(-8 * cus // tiles), 32))
+    while g > 1 and views // g < 8:
+        g -= 1
+    return g
+
+
+def job_scratch_bytes(spec: JobSpec, cus: int = 256) -> int:
+    """Device scratch one SIRT step of the job takes from the library's
+    buffers: the padded image copies and the back projection's partial sums,
+    in the quarter-turn form (views a multiple of 4 over 2 pi) or the plain
+    one.  Equal to fp_sirt_scratch_bytes for the job's geometry."""
+    n, nv = spec.n, spec.n_views
+    tiles = math.ceil(n / 16) * math.ceil(n / 32)
+    copies = 4 * n * 2 * (n + 32)          # row-major and transposed padded copies
+    if nv % 4 == 0:
+        partial = 4 * _view_groups(tiles, nv // 4, cus) * 4 * n * n
+    else:
+        g = _view_groups(tiles, nv, cus)
+        partial = 4 * g * n * n if g > 1 else 0
+    return -(-copies // 256) * 256 + partial
+
+
+def job_device_bytes(spec: JobSpec, cus: int = 256) -> int:
     """Upper estimate of the device memory a job holds while admitted: the
     FP32 per-ray tables (11 per ray), per-view and per-tile tables, the SIRT
-    weights, iterate, sinogram, residual and the padded image copies."""
+    weights, iterate, sinogram, residual and its share of the launch scratch
+    (job_scratch_bytes)."""
     rays = spec.n_views * spec.n_det
     pix = spec.n * spec.n
     tiles = math.ceil(spec.n / 16) * math.ceil(spec.n / 32)
     tables = 4 * 11 * rays + 16 * spec.n_views + 16 * spec.n_views * tiles
     weights = 4 * (rays + pix)
     buffers = 4 * (pix + 2 * rays)
-    pad = 4 * spec.n * 2 * (spec.n + 32)
-    return tables + weights + buffers + pad + 4 * 4096
+    return tables + weights + buffers + job_scratch_bytes(spec, cus) + 16 * 4096
 
 
 class RealClock:
@@ -158,7 +184,11 @@ class Server:
     hbm_budget: bytes the admitted jobs may hold together (a job larger than
     the budget is admitted alone when nothing else runs); max_active: slot
     limit; step_work: matrix entries one step may evaluate (the oldest job
-    always goes).
+    always goes); keep_outputs: True, False or the job ids whose final
+    iterates ``run`` returns.  With an executor that reports ``available_bytes()`` (the
+    device's free memory), a job is admitted only while its estimate also
+    fits that less `reserve` bytes; finished jobs whose memory the executor
+    still holds are flushed first.
 
     With an executor that can launch a step without waiting for it
     (``launch`` returning a token and ``wait`` on a token), the loop keeps
@@ -172,9 +202,11 @@ class Server:
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
                  step_work: float = 4e9, clock=None, keep_outputs: bool = False,
-                 depth: int = 2):
+                 depth: int = 2, reserve: int = 256 << 20, burst: int = 4):
         self.ex = executor
         self.budget = int(hbm_budget)
+        self.reserve = int(reserve)
+        self.burst = max(1, int(burst))
         self.max_active = int(max_active)
         self.step_work = float(step_work)
         self.clock = clock or RealClock()
@@ -195,7 +227,7 @@ class Server:
         def release_done():
             nonlocal used
             for a in done:
-                if self.keep_outputs:
+                if self._keep(a.spec.job_id):
                     res.outputs[a.spec.job_id] = self.ex.result(a.handle)
                 self.ex.release(a.handle)
                 used -= a.nbytes
@@ -218,7 +250,8 @@ class Server:
             while waiting and len(active) < self.max_active:
                 spec = waiting[0]
                 need = job_device_bytes(spec)
-                if (active or inflight or done) and used + need > self.budget:
+                fits = used + need <= self.budget and self._device_fits(need)
+                if (active or inflight or done) and not fits:
                     if done:                      # free finished jobs first
                         release_done()
                         continue
@@ -244,12 +277,18 @@ class Server:
                     batch.append(a)
                     work += w
                 handles = [a.handle for a in batch]
-                token = self.ex.launch(handles) if pipelined else self.ex.step(handles)
+                # with nobody waiting for admission, up to `burst` iterations
+                # of the batch go in one step (fewer host round trips)
+                iters = 1
+                if self.burst > 1 and not waiting:
+                    iters = min(self.burst, min(a.spec.iters - a.done_iters for a in batch))
+                fn = self.ex.launch if pipelined else self.ex.step
+                token = fn(handles, iters) if iters > 1 else fn(handles)
                 res.steps += 1
                 res.batch_sizes.append(len(batch))
                 finishing = []
                 for a in batch:
-                    a.done_iters += 1
+                    a.done_iters += iters
                     if a.done_iters >= a.spec.iters:
                         finishing.append(a)
                 if finishing:
@@ -269,6 +308,23 @@ class Server:
         if hasattr(self.ex, "flush"):
             self.ex.flush()
         return res
+
+    def _keep(self, job_id) -> bool:
+        """keep_outputs: True (every job), a collection of job ids, or False."""
+        k = self.keep_outputs
+        return bool(k) if isinstance(k, bool) else job_id in k
+
+    def _device_fits(self, need: int) -> bool:
+        """Whether `need` more bytes fit the device's free memory (always true
+        for an executor that does not report it); memory of released jobs the
+        executor still holds is given back first."""
+        if not hasattr(self.ex, "available_bytes"):
+            return True
+        if self.ex.available_bytes() - self.reserve >= need:
+            return True
+        if hasattr(self.ex, "flush"):
+            self.ex.flush()
+        return self.ex.available_bytes() - self.reserve >= need
 
 
 def run_plain(executor, trace, clock=None, keep_outputs: bool = False) -> ServeResult:
@@ -318,16 +374,20 @@ class GpuExecutor:
     whose forward projection has at least `solo_blocks` work-groups of 256
     rays with the single-job kernels, which also split the back projection
     over view groups, and groups the others in ``fp_sirt_step_multi``
-    launches.  Released jobs are destroyed `free_batch` at a time: destroying
-    a geometry synchronises the device, once per batch."""
+    launches.  Released jobs are destroyed `free_batch` at a time (one by one
+    by default: destroying a geometry does not wait; the library recycles its
+    memory once the job's queued work is done)."""
 
-    def __init__(self, device="cuda", solo_blocks: int | None = None, free_batch: int = 16):
+    def __init__(self, device="cuda", solo_blocks: int | None = None, free_batch: int = 1,
+                 keep_inputs: bool = False):
         import torch
 
         from . import fanproj
         self.torch = torch
         self.fp = fanproj
         self.device = torch.device(device)
+        self.keep_inputs = keep_inputs
+        self.inputs = {}         # job_id -> host copy of the job's sinogram (keep_inputs)
         if solo_blocks is None:
             solo_blocks = 8 * torch.cuda.get_device_properties(self.device).multi_processor_count
         self.solo_blocks = int(solo_blocks)
@@ -339,7 +399,7 @@ class GpuExecutor:
         grouped = []
         for h in handles:
             g, x, y, w = h
-            if g.n_views * -(-g.n_det // 256) >= self.solo_blocks:
+            if len(handles) == 1 or g.n_views * -(-g.n_det // 256) >= self.solo_blocks:
                 g.sirt_step(x, y, 1.0, w)
             else:
                 grouped.append(h)
@@ -354,6 +414,9 @@ class GpuExecutor:
         x = torch.zeros((g.ny, g.nx), device=self.device)
         w = torch.empty_like(y)
         self.fp.fp_sirt_prepare(g.handle)
+        k = self.keep_inputs
+        if (bool(k) if isinstance(k, bool) else spec.job_id in k):
+            self.inputs[spec.job_id] = y.cpu().numpy()
         # the step stream sees the prepared data; the tensors stay allocated
         # until its work on them is done
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
@@ -361,13 +424,15 @@ class GpuExecutor:
             t.record_stream(self.stream)
         return (g, x, y, w)
 
-    def step(self, handles) -> None:
-        self.launch(handles).synchronize()
+    def step(self, handles, iters: int = 1) -> None:
+        self.launch(handles, iters).synchronize()
 
-    def launch(self, handles):
-        """Queue one SIRT step of the jobs; returns an event recorded after it."""
+    def launch(self, handles, iters: int = 1):
+        """Queue `iters` SIRT iterations of the jobs; returns an event recorded
+        after them."""
         with self.torch.cuda.stream(self.stream):
-            self._queue(handles)
+            for _ in range(iters):
+                self._queue(handles)
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
         return ev
@@ -386,13 +451,21 @@ class GpuExecutor:
         self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return h[1].detach().clone()
 
+    def available_bytes(self) -> int:
+        """Free device memory: the device's own free bytes plus what torch's
+        caching allocator holds unused."""
+        torch = self.torch
+        free, _ = torch.cuda.mem_get_info(self.device)
+        cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+        return int(free + cached)
+
     def release(self, h) -> None:
         self._released.append(h)
         if len(self._released) >= self.free_batch:
             self.flush()
 
     def flush(self) -> None:
-        """Destroy the released jobs' geometries (one device synchronisation)."""
+        """Destroy the released jobs' geometries."""
         for g, *_ in self._released:
             g.close()
         self._released.clear()

@@ -6,6 +6,11 @@
   make_sirt_golden.py from the oracle only).
 * Two steps on the full 2048 x 2048 x 1440 x 2048 scan: sampled pixels of the
   iterate against stored oracle values.
+* 50 steps from zero on the full scan with its Poisson-noisy data (the
+  stored float32 log sinogram both sides read): the iterate at 16384 seeded
+  pixels, along the two central rows and the central column, and its norm,
+  against the stored oracle iterate (tests/golden/sirt50_large_*.npz, written
+  by make_sirt_golden.py --large50 from the oracle only), rel-L2 <= 1e-4.
 * 50 steps on the full scan: the R-weighted data residual never grows (a
   property of SIRT with 0 < lambda < 2), checked at several steps.
 """
@@ -83,6 +88,36 @@ def test_sirt2_large_sampled(fp, torch_cuda):
     e1, e2 = rel_l2(got1, ref["x1"]), rel_l2(got2, ref["x2"])
     print(f"large SIRT step 1 / 2 sampled rel-L2 {e1:.3e} / {e2:.3e}", flush=True)
     assert e1 <= 1e-5 and e2 <= 1e-5
+
+
+def test_sirt50_large_matches_stored_oracle(fp, torch_cuda):
+    import make_sirt_golden as mg
+    torch = torch_cuda
+    f_sino = os.path.join(GOLDEN, "sirt50_large_sino.npz")
+    f_ref = os.path.join(GOLDEN, "sirt50_large_sampled.npz")
+    if not (os.path.exists(f_sino) and os.path.exists(f_ref)):
+        pytest.skip("stored 50-step large-scan SIRT iterate not generated")
+    ref = np.load(f_ref)
+    s = workloads.LARGE
+    y = np.load(f_sino)["y"]
+    assert y.dtype == np.float32 and y.shape == (s.n_views, s.n_det)
+    pix = ref["pix"]
+    assert np.array_equal(pix, mg.large50_sample_positions(s.n))
+    g = fp.Geometry(**s.kwargs())
+    x = torch.zeros((s.n, s.n), dtype=torch.float32, device="cuda")
+    yt = torch.from_numpy(y).cuda()
+    work = torch.empty_like(yt)
+    for _ in range(int(ref["iters"])):
+        g.sirt_step(x, yt, 1.0, work)
+    xc = x.cpu().numpy().astype(np.float64)
+    e_pix = rel_l2(xc[pix[:, 1], pix[:, 0]], ref["x"])
+    e_rows = rel_l2(xc[ref["row_index"], :], ref["rows"])
+    e_col = rel_l2(xc[:, int(ref["col_index"])], ref["col"])
+    e_norm = abs(np.sqrt(np.sum(xc * xc)) / np.sqrt(float(ref["sumsq"])) - 1.0)
+    print(f"large SIRT-{int(ref['iters'])} vs oracle: {len(pix)} pixels rel-L2 {e_pix:.3e}, "
+          f"central rows {e_rows:.3e}, central column {e_col:.3e}, norm {e_norm:.3e} "
+          f"(quarter-turn form {g.quarter_turn()})", flush=True)
+    assert max(e_pix, e_rows, e_col, e_norm) <= 1e-4
 
 
 def test_sirt50_large_residual_decreases(fp, torch_cuda):

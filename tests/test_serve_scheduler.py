@@ -14,6 +14,7 @@ class FakeExecutor:
         self.clock, self.overhead, self.unit, self.width = clock, overhead, unit, width
         self.live = {}
         self.log = []
+        self.step_iters = []    # iterations of each logged step
 
     def work(self, spec):
         return spec.n * spec.n * spec.n_views * 3 * self.unit
@@ -23,11 +24,13 @@ class FakeExecutor:
         self.log.append(("prepare", spec.job_id, self.clock.now()))
         return spec.job_id
 
-    def step(self, handles):
+    def step(self, handles, iters=1):
         tot = sum(self.work(self.live[h]) for h in handles)
         big = max(self.work(self.live[h]) for h in handles)
-        self.clock.advance(self.overhead + max(tot / self.width, big))
+        for _ in range(iters):
+            self.clock.advance(self.overhead + max(tot / self.width, big))
         self.log.append(("step", tuple(handles), self.clock.now()))
+        self.step_iters.append(iters)
 
     def run_job(self, h, iters):
         for _ in range(iters):
@@ -139,6 +142,7 @@ def test_step_work_budget_keeps_fifo_priority():
     assert len(res.latency) == 30
     order = {j: k for k, j in enumerate(res.order)}
     iterating, steps = set(), {}
+    step_iters = iter(ex.step_iters)
     for kind, handles, _ in ex.log:
         if kind == "prepare":
             iterating.add(handles)
@@ -146,8 +150,10 @@ def test_step_work_budget_keeps_fifo_priority():
             ks = [order[h] for h in handles]
             assert ks == sorted(ks)                           # admission order
             assert ks[0] == min(order[h] for h in iterating)  # the oldest unfinished job
+            n_it = next(step_iters)
             for h in handles:
-                steps[h] = steps.get(h, 0) + 1
+                steps[h] = steps.get(h, 0) + n_it
+                assert steps[h] <= trace[h].iters
                 if steps[h] == trace[h].iters:
                     iterating.discard(h)
             tot = sum(serve.job_iteration_work(trace[h]) for h in handles)
@@ -163,9 +169,10 @@ class SaturatingExecutor(FakeExecutor):
         super().__init__(clock, **kw)
         self.sat = sat
 
-    def step(self, handles):
+    def step(self, handles, iters=1):
         tot = sum(self.work(self.live[h]) for h in handles)
-        self.clock.advance(self.overhead + max(tot, self.sat) / self.width)
+        for _ in range(iters):
+            self.clock.advance(self.overhead + max(tot, self.sat) / self.width)
         self.log.append(("step", tuple(handles), self.clock.now()))
 
 
@@ -196,13 +203,14 @@ class AsyncFakeExecutor(FakeExecutor):
         self.host = host
         self.busy_until = 0.0
 
-    def launch(self, handles):
+    def launch(self, handles, iters=1):
         tot = sum(self.work(self.live[h]) for h in handles)
         big = max(self.work(self.live[h]) for h in handles)
         self.clock.advance(self.host)
         start = max(self.busy_until, self.clock.now())
-        self.busy_until = start + max(tot / self.width, big)
+        self.busy_until = start + iters * max(tot / self.width, big)
         self.log.append(("step", tuple(handles), self.busy_until))
+        self.step_iters.append(iters)
         return self.busy_until
 
     def wait(self, token):
@@ -231,6 +239,7 @@ def test_pipelined_loop_is_complete_and_within_budget():
     steps = {}
     live, used = set(), 0
     sizes = {s.job_id: serve.job_device_bytes(s) for s in trace}
+    step_iters = iter(ex.step_iters)
     for kind, x, t in ex.log:
         if kind == "prepare":
             live.add(x)
@@ -240,9 +249,10 @@ def test_pipelined_loop_is_complete_and_within_budget():
             live.discard(x)
             used -= sizes[x]
         else:
+            n_it = next(step_iters)
             for h in x:
                 assert h in live
-                steps[h] = steps.get(h, 0) + 1
+                steps[h] = steps.get(h, 0) + n_it
     assert all(steps[s.job_id] == s.iters for s in trace)
     for s in trace:        # a job completes no earlier than its last step ends
         last = max(t for kind, x, t in ex.log if kind == "step" and s.job_id in x)
@@ -262,3 +272,19 @@ def test_pipelining_overlaps_host_and_device():
                         clock=c2).run(trace)
     assert pipe.makespan < sync.makespan
     assert serve.latency_stats(pipe)["mean_s"] < serve.latency_stats(sync)["mean_s"]
+
+
+def test_bursts_only_when_nobody_waits():
+    """With an empty admission queue a step may advance its jobs by several
+    iterations at once (never past a job's last); a job waiting for admission
+    turns bursts off."""
+    clock = serve.SimClock()
+    ex = FakeExecutor(clock)
+    trace = _trace(count=12, rate=5.0, iters=10)
+    res = serve.Server(ex, hbm_budget=1 << 40, clock=clock, burst=4).run(trace)
+    assert len(res.latency) == 12
+    assert max(ex.step_iters) == 4 and min(ex.step_iters) >= 1
+    clock = serve.SimClock()
+    ex1 = FakeExecutor(clock)
+    serve.Server(ex1, hbm_budget=1 << 40, clock=clock, burst=1).run(trace)
+    assert set(ex1.step_iters) == {1}
