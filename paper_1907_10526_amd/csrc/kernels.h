@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void pad_kernel(const Real *__restrict__ img,
 }
 
 // ---------------------------------------------------------------------------
-// Forward projection: thread = ray (view blockIdx.y, cell m).
+// Forward projection: thread = ray (view blockIdx.x, cell m).
 // ---------------------------------------------------------------------------
 template <typename Real>
 struct RayWalk {
@@ -675,11 +675,12 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
 }
 
 template <typename Real, int NB, FwdMode MODE, int S>
-__global__ __launch_bounds__(kFwdThreads, S == 1 ? min_waves(NB, sizeof(Real)) : 1) void forward_kernel(
+// (the quarter-turn walk of one image at 6 waves per SIMD, 80 VGPRs)
+__global__ __launch_bounds__(kFwdThreads, S == 1 ? min_waves(NB, sizeof(Real)) : NB == 1 ? 6 : 1) void forward_kernel(
     DevGeom G, const Real *__restrict__ copies,
     Real *__restrict__ out, int *__restrict__ counts, const Real *__restrict__ y_meas,
     const Real *__restrict__ row_w) {
-    forward_block<Real, NB, MODE, S>(G, blockIdx.y, blockIdx.x, copies, out, counts, y_meas,
+    forward_block<Real, NB, MODE, S>(G, blockIdx.x, blockIdx.y, copies, out, counts, y_meas,
                                      row_w);
 }
 

@@ -37,14 +37,14 @@ __global__ __launch_bounds__(256) void pad_multi_kernel(const MultiArgs A) {
 // The forward residuals of every job; R = 1 (plain) or 4 (quarter-turn form:
 // the forward walk's rotations, see forward_block).
 template <int R>
-__global__ __launch_bounds__(kFwdThreads, R == 1 ? 8 : 1) void forward_multi_kernel(
+__global__ __launch_bounds__(kFwdThreads, R == 1 ? 8 : 6) void forward_multi_kernel(
     const MultiArgs A) {
     const int j = multi_job_of(A, blockIdx.x);
     const MultiJob &J = A.job[j];
     const unsigned local = blockIdx.x - J.fwd_begin;
-    constexpr int kRays = fwd_rays_per_block(R);
-    const unsigned bx = (J.g.nd + kRays - 1) / kRays;
-    forward_block<float, 1, FwdMode::kSirtResidual, R>(J.g, local / bx, local % bx, J.copies,
+    // (views fastest, as in the single-job launch)
+    const unsigned nv = (unsigned)J.g.nv;
+    forward_block<float, 1, FwdMode::kSirtResidual, R>(J.g, local % nv, local / nv, J.copies,
                                                       J.work, nullptr, J.y_meas, J.row_w);
 }
 
