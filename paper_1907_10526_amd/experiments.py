@@ -169,10 +169,14 @@ def _sirt(torch, fwd, back, y, shape, iters):
     return x
 
 
-def reconstruction(iters=300, beam="flat"):
+RECONSTRUCTION_RUNS = ((128, 409, 200.0, 16, 81), (256, 815, 400.0, 30, 82))
+
+
+def reconstruction(iters=300, beam="flat", runs=RECONSTRUCTION_RUNS):
+    """runs: (image size, cells, D_po, views, phantom seed) per reconstruction."""
     torch = _torch()
     out = []
-    for n, nd, dpo, nv, seed in [(128, 409, 200.0, 16, 81), (256, 815, 400.0, 30, 82)]:
+    for n, nd, dpo, nv, seed in runs:
         ang = np.arange(nv) * (2 * math.pi / nv)
         g = _geom(n, dpo, 2 * dpo, ang, nd, 1.0, pitch=1.0, beam=beam)
         truth = _phantom(n, seed)

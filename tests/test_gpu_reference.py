@@ -117,3 +117,64 @@ def test_experiments_run_small(torch_cuda):
     ie = experiments.image_error()
     small, large = ie["images"]
     assert small["rel_l2"] < 1e-2 and large["rel_l2"] < small["rel_l2"], ie
+
+
+def _oracle_max_error(oracle_mod, n, ny, i, j, angs, nd, tau, pitch, dsc, dsd):
+    """e(u) of Sec. V-A from the oracle's CNSF entries and the exact reference
+    chord integral, over the cells around the pixel's shadow."""
+    g = oracle_mod.Geometry(n, ny, 1.0, dsc, dsd, angs, nd, tau, det_spacing=pitch)
+    lo, hi = eg.pixel_box(i, j, n, ny, 1.0)
+    out = []
+    for v, th in enumerate(angs):
+        hit = [m for m in range(nd) if g.entry(v, m, i, j) != 0.0]
+        cells = range(max(0, hit[0] - 3), min(nd, hit[-1] + 4))
+        out.append(max(abs(g.entry(v, m, i, j)
+                           - eg.ref_entry(th, dsc, dsd, (m - 0.5 * (nd - 1)) * pitch, tau, lo, hi))
+                       for m in cells))
+    return np.array(out)
+
+
+def test_max_error_driver_matches_oracle(torch_cuda, oracle_mod):
+    """The e(u) curves of the max-error experiment (pixel at the centre, 90
+    angles over a quarter turn; pixel at (100.5, 50.5), 360 angles) equal the
+    oracle's CNSF entries against the exact reference at every tenth angle."""
+    from paper_1907_10526_amd import experiments
+    me = experiments.max_error()
+    c, o = me["pixel_0_0"], me["pixel_100.5_50.5"]
+    assert len(c["e_per_angle"]) == 90 and len(o["e_per_angle"]) == 360
+    assert c["max"] == max(c["e_per_angle"]) and o["max"] == max(o["e_per_angle"])
+    ks = np.arange(0, 90, 10)
+    want = _oracle_max_error(oracle_mod, 1, 1, 0, 0, ks * (0.5 * math.pi / 90), 64, 0.5, 0.5,
+                             200.0, 400.0)
+    got = np.array(c["e_per_angle"])[ks]
+    assert np.max(np.abs(got - want)) <= 1e-9, (got, want)
+    ks = np.arange(0, 360, 30)
+    want = _oracle_max_error(oracle_mod, 202, 102, 201, 101, ks * (2 * math.pi / 360), 2200, 0.5,
+                             0.5, 200.0, 400.0)
+    got = np.array(o["e_per_angle"])[ks]
+    assert np.max(np.abs(got - want)) <= 1e-9, (got, want)
+    print(f"max error: centre {c['max']:.3e}, offset {o['max']:.3e}", flush=True)
+
+
+def test_reconstruction_driver_matches_oracle(torch_cuda, fp, oracle_mod):
+    """The reconstruction experiment on a reduced scan (64 x 64, 205 cells,
+    12 views, 40 steps): its CNSF SIRT matches the oracle's SIRT on the same
+    reference data (SNR to 1e-6 dB), and, as the paper reports, CNSF and the
+    reference operators reconstruct to the same SNR."""
+    from paper_1907_10526_amd import experiments
+    torch = torch_cuda
+    n, nd, dpo, nv, seed, iters = 64, 205, 100.0, 12, 83, 40
+    res = experiments.reconstruction(iters=iters, runs=[(n, nd, dpo, nv, seed)])["runs"][0]
+    ang = np.arange(nv) * (2 * math.pi / nv)
+    g = fp.Geometry(n, n, 1.0, dpo, 2 * dpo, ang, nd, 1.0, det_pitch=1.0)
+    truth = experiments._phantom(n, seed)
+    y = g.forward_reference(torch.from_numpy(truth).cuda()).cpu().numpy()
+    og = oracle_mod.Geometry(n, n, 1.0, dpo, 2 * dpo, ang, nd, 1.0, det_spacing=1.0)
+    x = og.sirt(y, iters)
+    snr = float(10.0 * np.log10(np.sum(truth ** 2) / np.sum((x - truth) ** 2)))
+    print(f"reconstruction: SNR ref {res['snr_db']['ref']:.4f} dB, cnsf {res['snr_db']['cnsf']:.4f} "
+          f"dB, oracle {snr:.4f} dB, cnsf-ref rel-L2 {res['cnsf_minus_ref_rel_l2']:.2e}", flush=True)
+    assert abs(res["snr_db"]["cnsf"] - snr) <= 1e-6
+    assert abs(res["snr_db"]["cnsf"] - res["snr_db"]["ref"]) <= 0.05
+    assert res["cnsf_minus_ref_rel_l2"] <= 1e-2
+    assert res["snr_db"]["ref"] > 5.0
