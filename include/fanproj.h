@@ -304,6 +304,24 @@ size_t fp_geometry_device_bytes(const fp_geometry *g);
  * reference projector always evaluate every view. */
 int32_t fp_geometry_quarter_turn(const fp_geometry *g);
 
+/* Order of the scan symmetry the geometry's FP32 projections and SIRT steps
+ * use: 8 (the quarter turns and the reflection across the image diagonal),
+ * 4 (the quarter turns only, see fp_geometry_quarter_turn), 1 (none); 0 for
+ * NULL.  Order 8 needs a quarter-turn symmetric scan that the reflection
+ * across x = y also leaves unchanged: n_views a multiple of 8 and view Q - v
+ * at pi/2 minus the angle of view v (Q = n_views / 4; e.g. views
+ * 2 pi v / n_views).  The reflection takes the source at angle t to pi/2 - t
+ * and detector coordinate s to -s (the cells lie symmetrically about the
+ * detector centre), so entry A_{(Q - v, n_det-1-m), D p} equals
+ * A_{(v, m), p} with D the reflection of the pixel grid.  With order 8 the
+ * back projection of one image (fp_back and the update half of fp_sirt_step
+ * with batch 1) evaluates each entry once for eight views (views 0 and Q/2,
+ * their own reflections, four); batches of several images, the forward
+ * projection and the grouped SIRT step (fp_sirt_step_multi) run in the
+ * quarter-turn form.  All forms give the plain form's results to FP32
+ * rounding. */
+int32_t fp_geometry_symmetry(const fp_geometry *g);
+
 /* Text for the last non-OK status returned on the calling thread ("" if
  * none).  The pointer stays valid until the thread's next fanproj call. */
 const char *fp_last_error(void);

@@ -56,6 +56,27 @@ hipError_t launch_back_quarter(const DevGeom &g, BackMode mode, int nb, const fl
     return hipErrorInvalidValue;
 }
 
+size_t back_octant_work_bytes(const DevGeom &g) {
+    return (size_t)g.back_groups * 8 * g.nx * g.ny * sizeof(float);
+}
+
+hipError_t launch_back_octant(const DevGeom &g, BackMode mode, const float *sino, float *img,
+                              float *partial, const float *col_w, float relaxation,
+                              hipStream_t stream) {
+    switch (g.beam) {
+        case FP_FAN_FLAT:
+            return launch_back_octant_beam<FP_FAN_FLAT>(g, mode, sino, img, partial, col_w,
+                                                        relaxation, stream);
+        case FP_FAN_ARC:
+            return launch_back_octant_beam<FP_FAN_ARC>(g, mode, sino, img, partial, col_w,
+                                                       relaxation, stream);
+        case FP_PARALLEL:
+            return launch_back_octant_beam<FP_PARALLEL>(g, mode, sino, img, partial, col_w,
+                                                        relaxation, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
 #define FANPROJ_INSTANTIATE(Real)                                                                  \
     template int back_max_batch<Real>(const DevGeom &);                                            \
     template size_t back_work_bytes<Real>(const DevGeom &, int);                                   \

@@ -1,5 +1,6 @@
-// Back projection kernels for the flat detector, FP32, and their quarter-turn form.
+// Back projection kernels for the flat detector, FP32, and their quarter-turn and octant forms.
 #include "back_launch.h"
 
 FANPROJ_INSTANTIATE_BACK(float, FP_FAN_FLAT)
 FANPROJ_INSTANTIATE_BACK_QUARTER(FP_FAN_FLAT)
+FANPROJ_INSTANTIATE_BACK_OCTANT(FP_FAN_FLAT)

@@ -108,7 +108,57 @@ hipError_t launch_back_quarter_nb(const DevGeom &g, int nbi, const float *sino, 
     }
 }
 
+// Octant form (FP32, one image): the back kernel over g (the base views) with
+// the four rotations and the four reflections of each base view as 8
+// images, its sums into `partial`, then the finalize that combines them.
+template <int CAP, BackMode MODE, int BEAM>
+hipError_t launch_back_octant_t(const DevGeom &g, const float *sino, float *img, float *partial,
+                                const float *col_w, float relaxation, hipStream_t stream) {
+    if constexpr (!back_fits<float, 8, CAP>()) {
+        return hipErrorInvalidValue;  // excluded at geometry creation
+    } else {
+        const int groups = g.back_groups;
+        dim3 grid((unsigned)(g.tiles_x * g.tiles_y * groups));
+        hipLaunchKernelGGL((back_kernel<float, 8, CAP, BackMode::kPlain, BEAM>), grid,
+                           dim3(kBackThreads), 0, stream, g, sino, img, partial, col_w,
+                           relaxation, 1);
+        const int n = g.nx;
+        dim3 fgrid((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32));
+        hipLaunchKernelGGL((back_finalize_octant_kernel<MODE>), fgrid, dim3(32, 32), 0, stream,
+                           partial, groups, n, img, col_w, relaxation);
+        return hipGetLastError();
+    }
+}
+
+template <BackMode MODE, int BEAM>
+hipError_t launch_back_octant_cap(const DevGeom &g, const float *sino, float *img, float *partial,
+                                  const float *col_w, float relaxation, hipStream_t stream) {
+    switch (g.back_cap) {
+        case 64: return launch_back_octant_t<64, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 128: return launch_back_octant_t<128, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 256: return launch_back_octant_t<256, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        case 512: return launch_back_octant_t<512, MODE, BEAM>(g, sino, img, partial, col_w, relaxation, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+template <int BEAM>
+hipError_t launch_back_octant_beam(const DevGeom &g, BackMode mode, const float *sino, float *img,
+                                   float *partial, const float *col_w, float relaxation,
+                                   hipStream_t stream) {
+    switch (mode) {
+        case BackMode::kPlain:
+            return launch_back_octant_cap<BackMode::kPlain, BEAM>(g, sino, img, partial, col_w,
+                                                                  relaxation, stream);
+        case BackMode::kSirtUpdate:
+            return launch_back_octant_cap<BackMode::kSirtUpdate, BEAM>(g, sino, img, partial,
+                                                                       col_w, relaxation, stream);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
 
 template <int BEAM>
 hipError_t launch_back_quarter_beam(const DevGeom &g, BackMode mode, int nbi, const float *sino,
@@ -153,4 +203,8 @@ hipError_t launch_back_beam(const DevGeom &g, BackMode mode, int nb, const Real 
 #define FANPROJ_INSTANTIATE_BACK_QUARTER(BEAM)                                                    \
     template hipError_t fanproj::launch_back_quarter_beam<BEAM>(                                  \
         const fanproj::DevGeom &, fanproj::BackMode, int, const float *, float *, float *,        \
+        const float *, float, hipStream_t);
+#define FANPROJ_INSTANTIATE_BACK_OCTANT(BEAM)                                                     \
+    template hipError_t fanproj::launch_back_octant_beam<BEAM>(                                   \
+        const fanproj::DevGeom &, fanproj::BackMode, const float *, float *, float *,             \
         const float *, float, hipStream_t);

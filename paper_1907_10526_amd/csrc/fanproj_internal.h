@@ -114,6 +114,9 @@ struct DevGeom {
     int max_cells;           // largest per-(view, tile) cell range
     int back_cap;            // LDS capacity (cells) of the back kernel in use
     int back_groups;         // view groups of the back projection (>= 1)
+    // Octant form only (nv = quarter_views / 2 + 1 base views of a scan of
+    // 4 quarter_views views): views per quarter turn; 0 in the other forms.
+    int quarter_views;
     int beam;                // FP_FAN_FLAT, FP_FAN_ARC or FP_PARALLEL
     double pixel;            // delta
     double dsc, dsd;         // source-centre, source-detector distances
@@ -228,6 +231,35 @@ hipError_t launch_back_quarter_beam(const DevGeom &g, BackMode mode, int nb, con
                                     float *img, float *partial, const float *col_w,
                                     float relaxation, hipStream_t stream);
 
+// Octant form of the back projection (FP32, one image per launch) for a
+// quarter-turn symmetric scan that is also unchanged by the reflection
+// across the image diagonal x = y: views t_v and t_{Q-v} with
+// t_v + t_{Q-v} = pi/2 (Q = nv_scan / 4; then nv_scan % 8 == 0) and cells
+// symmetric about the detector centre.  The reflection D(i, j) = (j, i)
+// takes ray (v, m) to ray (Q - v, nd-1-m), so with the quarter turns the
+// entry A_{(v,m),p} also equals A_{((Q - v + k Q) mod 4Q, nd-1-m), R^k D p}:
+// each entry is evaluated once for eight views.  g describes the base views
+// 0 .. Q/2 (a prefix of the full tables, quarter_views = Q); views 0 and
+// Q/2 are their own reflections and serve four views.  Modes kPlain and
+// kSirtUpdate, `partial` of back_octant_work_bytes(g) bytes.  (The forward
+// projection of such a scan runs in the quarter-turn form: its ray walk
+// reads one pixel value per non-zero entry in either form, and those reads,
+// not the entry arithmetic, bound it.)
+size_t back_octant_work_bytes(const DevGeom &g);
+hipError_t launch_back_octant(const DevGeom &g, BackMode mode, const float *sino, float *img,
+                              float *partial, const float *col_w, float relaxation,
+                              hipStream_t stream);
+template <int BEAM>
+hipError_t launch_back_octant_beam(const DevGeom &g, BackMode mode, const float *sino,
+                                   float *img, float *partial, const float *col_w,
+                                   float relaxation, hipStream_t stream);
+
+// The form a single-geometry SIRT step runs in: every view on its own, the
+// quarter-turn form (four views per evaluated entry), or the quarter-turn
+// forward with the octant back projection (eight views per evaluated entry
+// of the back projection).
+enum class Form : int { kPlain = 0, kQuarter = 1, kOctant = 2 };
+
 // Grouped SIRT step: several jobs, each with its own geometry; one launch
 // for the padded copies and one for the forward residuals of all of them,
 // then each job's back update.  Up to kMaxJobsPerLaunch job descriptors
@@ -286,6 +318,13 @@ struct fp_geometry {
     // SIRT steps then run in the quarter-turn form.
     bool quarter = false;
     fanproj::DevGeom dev_quarter{};
+    // Octant symmetry (quarter-turn symmetric and unchanged by the reflection
+    // across the diagonal): dev_octant is dev restricted to the views
+    // 0 .. nv / 8 with quarter_views = nv / 4; single-image FP32 back
+    // projections (and the back half of single-image SIRT steps) then run in
+    // the octant form.
+    bool octant = false;
+    fanproj::DevGeom dev_octant{};
     void *table_block = nullptr;   // one device allocation for the FP32 tables
     size_t table_bytes = 0, table_cap = 0;   // bytes used, bytes of the block
     // FP64 per-ray tables, built on the first FP64 call.
@@ -335,20 +374,23 @@ class DeviceGuard {
 
 // The parts of the SIRT step shared by the SIRT entry points (abi.cpp).
 // sirt_check: the argument checks of fp_sirt_step (geometry, batch,
-// relaxation, device pointers).  `quarter` selects the quarter-turn form
-// (only for a geometry with g->quarter) or the plain one.  sirt_max_chunk:
-// the largest batch chunk one launch pair takes.  sirt_scratch_bytes: device
+// relaxation, device pointers).  sirt_form: the form a step of `batch`
+// images runs in (the octant form for one image where the geometry has it;
+// else the quarter-turn form where the geometry has it; else the plain
+// one); `form` below must be one the geometry has.  sirt_max_chunk: the
+// largest batch chunk one launch pair takes.  sirt_scratch_bytes: device
 // scratch one step needs for chunks of nb images (padded copies, then
 // view-group partials at *partial_offset).  sirt_step_launch: the launches,
 // in chunks of at most max_nb images, with `scratch` of
-// sirt_scratch_bytes(g, max_nb, quarter) bytes; the weights must have been
+// sirt_scratch_bytes(g, max_nb, form) bytes; the weights must have been
 // built.
 fp_status sirt_check(const fp_geometry *g, const float *image, const float *sino_meas,
                      float relaxation, const float *work, int32_t batch, const char *fn);
-int sirt_max_chunk(const fp_geometry *g, bool quarter);
-size_t sirt_scratch_bytes(const fp_geometry *g, int nb, bool quarter, size_t *partial_offset);
+Form sirt_form(const fp_geometry *g, int32_t batch);
+int sirt_max_chunk(const fp_geometry *g, Form form);
+size_t sirt_scratch_bytes(const fp_geometry *g, int nb, Form form, size_t *partial_offset);
 fp_status sirt_step_launch(const fp_geometry *g, float *image, const float *sino_meas,
-                           float relaxation, float *work, int32_t batch, int max_nb, bool quarter,
+                           float relaxation, float *work, int32_t batch, int max_nb, Form form,
                            void *scratch, hipStream_t s, const char *fn);
 
 // The reference projector (reference.hip): forward (true) or its adjoint

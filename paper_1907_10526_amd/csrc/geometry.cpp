@@ -41,6 +41,23 @@ bool quarter_turn_symmetric(int nx, int ny, int n_views, const double *angles) {
     return true;
 }
 
+// Whether a quarter-turn symmetric scan of n_views views (n_views % 8 == 0)
+// is also unchanged by the reflection across the diagonal x = y: the
+// reflection takes the source at angle t to pi/2 - t and detector coordinate
+// s to -s (the cells are symmetric about the detector centre), so every view
+// v of the first quarter needs its partner Q - v at pi/2 - t_v (Q =
+// n_views / 4; to 1e-13 rad).  The octant form of the back projection then
+// evaluates each entry once for eight views.
+bool octant_symmetric(int n_views, const double *angles) {
+    if (n_views % 8 != 0) return false;
+    const int q = n_views / 4;
+    for (int v = 0; v <= q; ++v) {
+        const double d = angles[v % n_views] + angles[(q - v) % n_views] - 0.5 * M_PI;
+        if (!(std::fabs(std::remainder(d, 2.0 * M_PI)) <= 1e-13)) return false;
+    }
+    return true;
+}
+
 }  // namespace
 
 fp_status ensure_f64_tables(fp_geometry *g) {
@@ -287,6 +304,14 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
         g->dev_quarter.nv = n_views / 4;
         g->dev_quarter.back_groups = view_groups(ntiles, n_views / 4, cus);
     }
+    g->octant = g->quarter && octant_symmetric(n_views, view_angles) &&
+                back_max_batch<float>(d) >= 8;
+    if (g->octant) {
+        g->dev_octant = d;
+        g->dev_octant.nv = n_views / 8 + 1;
+        g->dev_octant.quarter_views = n_views / 4;
+        g->dev_octant.back_groups = view_groups(ntiles, n_views / 8 + 1, cus);
+    }
     *out = g.release();
     return FP_OK;
 }
@@ -326,3 +351,8 @@ extern "C" size_t fp_geometry_device_bytes(const fp_geometry *g) {
 }
 
 extern "C" int32_t fp_geometry_quarter_turn(const fp_geometry *g) { return g && g->quarter ? 1 : 0; }
+
+extern "C" int32_t fp_geometry_symmetry(const fp_geometry *g) {
+    if (!g) return 0;
+    return g->octant ? 8 : g->quarter ? 4 : 1;
+}

@@ -728,7 +728,11 @@ static_assert(sizeof(BackLds<float, 1, 64>) == back_lds_values(1) * 64 * sizeof(
               "back-projection staging size");
 
 // Staged cell idx holds cell M0 - kBackPad + idx; the kBackPad cells on either
-// side of [M0, M0 + cnt) get zero weight and harmless constants.
+// side of [M0, M0 + cnt) get zero weight and harmless constants.  Image b
+// reads sino + b nrays.  In the octant form (NB = 8, G.quarter_views = Q >
+// 0, nrays = Q nd) images 4 + k read the reflected rays instead,
+// ((Q - v + k Q) mod 4Q, nd-1-m), with weight zero for the views that are
+// their own reflections (v = 0 and v = Q/2, the first and last of G).
 template <typename Real, int NB, int CAP, BackMode MODE>
 __device__ __forceinline__ void back_prefetch(const DevGeom &G, const RayTables<Real> &tab,
                                               const Real *__restrict__ sino, int v, int tile,
@@ -761,8 +765,23 @@ __device__ __forceinline__ void back_prefetch(const DevGeom &G, const RayTables<
             const Real wb = at(tab.bwg());
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const Real w = (MODE == BackMode::kOnes ? Real(1) : at(sino + b * nrays)) * wb;
-                st.w[k][b] = c == cc ? w : Real(0);
+                Real y;
+                if constexpr (MODE == BackMode::kOnes) {
+                    y = Real(1);
+                } else if constexpr (NB == 8) {
+                    const int Q = G.quarter_views;
+                    if (b < 4 || Q == 0) {
+                        y = at(sino + b * nrays);
+                    } else if (v > 0 && v < G.nv - 1) {
+                        const unsigned row = (unsigned)(Q - v + (b - 4) * Q);
+                        y = sino[(size_t)row * G.nd + (unsigned)(G.nd - 1 - M0 - cc)];
+                    } else {
+                        y = Real(0);
+                    }
+                } else {
+                    y = at(sino + b * nrays);
+                }
+                st.w[k][b] = c == cc ? y * wb : Real(0);
             }
         }
     }
@@ -910,7 +929,9 @@ __device__ __forceinline__ void back_block(BackLds<Real, NB, CAP> (&lds)[2], con
     const int tile = ty * G.tiles_x + tx;
     const int ntiles = G.tiles_x * G.tiles_y;
     const size_t npix = (size_t)G.nx * G.ny;
-    const size_t nrays = (size_t)G.nv * G.nd;
+    // sinogram values between the images of the batch (octant form: between
+    // the quarter turns of the one image)
+    const size_t nrays = (size_t)(G.quarter_views > 0 ? G.quarter_views : G.nv) * G.nd;
     const int v_begin = (int)(((long)G.nv * group) / groups);
     const int v_end = (int)(((long)G.nv * (group + 1)) / groups);
     constexpr int P = kBackPixPerThread;
@@ -1181,6 +1202,68 @@ __global__ __launch_bounds__(1024) void back_finalize_quarter_kernel(
     const float *__restrict__ col_w, float relaxation) {
     finalize_quarter_tile<MODE>(partial, groups, nb4, n, blockIdx.z, blockIdx.x * 32,
                                 blockIdx.y * 32, img, col_w, relaxation);
+}
+
+// Octant form of the back projection (one image): the back kernel ran over
+// the base views v = 0 .. Q/2 with the sinogram rows v + k Q as image k and
+// the reflected rays ((Q - v + k Q) mod 4Q, nd-1-m) as image 4 + k (k < 4),
+// so its sum for image k at pixel p is the contribution of views v + k Q at
+// R^k p, and for image 4 + k that of the reflected views at R^k D p
+// (D(i, j) = (j, i)).  Pixel q = (i, j) of the result is therefore
+//   sum_g sum_k [P_k(R^-k q) + M_k(D R^-k q)]
+//   = sum_g [P_0(i, j) + P_1(j, n-1-i) + P_2(n-1-i, n-1-j) + P_3(n-1-j, i)
+//          + M_0(j, i) + M_1(n-1-i, j) + M_2(n-1-j, n-1-i) + M_3(i, n-1-j)],
+// P_k = image k and M_k = image 4 + k of the group-g partials, at (column,
+// row).  Block (32, 32) finishes a 32 x 32 tile, one pixel per thread; the
+// four terms with swapped coordinates go through LDS so that every global
+// access is coalesced.  Sums in a fixed order.
+template <BackMode MODE>
+__global__ __launch_bounds__(1024) void back_finalize_octant_kernel(
+    const float *__restrict__ partial, int groups, int n, float *__restrict__ img,
+    const float *__restrict__ col_w, float relaxation) {
+    __shared__ float t[4][32][33];
+    const size_t npix = (size_t)n * n;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    auto part = [&](int g, int k) { return partial + ((size_t)g * 8 + k) * npix; };
+    // t[.][a][b], a = ty, b = tx (reads along b): P_1(j0 + b, n-1-i0-a),
+    // P_3(n-1-j0-b, i0 + a), M_0(j0 + b, i0 + a), M_2(n-1-j0-b, n-1-i0-a)
+    {
+        float s1 = 0.0f, s3 = 0.0f, s4 = 0.0f, s6 = 0.0f;
+        if (i0 + ty < n && j0 + tx < n) {
+            const size_t ra = (size_t)(n - 1 - i0 - ty) * n, rb = (size_t)(i0 + ty) * n;
+            const int ca = j0 + tx, cb = n - 1 - j0 - tx;
+            for (int g = 0; g < groups; ++g) {
+                s1 += part(g, 1)[ra + ca];
+                s3 += part(g, 3)[rb + cb];
+                s4 += part(g, 4)[rb + ca];
+                s6 += part(g, 6)[ra + cb];
+            }
+        }
+        t[0][ty][tx] = s1;
+        t[1][ty][tx] = s3;
+        t[2][ty][tx] = s4;
+        t[3][ty][tx] = s6;
+    }
+    __syncthreads();
+    const int i = i0 + tx, j = j0 + ty;
+    if (i >= n || j >= n) return;
+    float z0 = 0.0f, z2 = 0.0f, z5 = 0.0f, z7 = 0.0f;
+    for (int g = 0; g < groups; ++g) {
+        z0 += part(g, 0)[(size_t)j * n + i];
+        z2 += part(g, 2)[(size_t)(n - 1 - j) * n + (n - 1 - i)];
+        z5 += part(g, 5)[(size_t)j * n + (n - 1 - i)];
+        z7 += part(g, 7)[(size_t)(n - 1 - j) * n + i];
+    }
+    const float zr = ((z0 + t[0][tx][ty]) + z2) + t[1][tx][ty];
+    const float zm = ((t[2][tx][ty] + z5) + t[3][tx][ty]) + z7;
+    const float z = zr + zm;
+    const size_t pix = (size_t)j * n + i;
+    if constexpr (MODE == BackMode::kPlain) {
+        img[pix] = z;
+    } else {  // kSirtUpdate
+        img[pix] += relaxation * col_w[pix] * z;
+    }
 }
 
 }  // namespace

@@ -42,9 +42,9 @@ fp_status scratch_address(int dev, void **out, const char *fn) {
 }
 
 // The largest batch chunk (a power of two) whose scratch fits the array.
-int fitting_chunk(const fp_geometry *g, bool quarter) {
-    int nb = sirt_max_chunk(g, quarter);
-    while (nb > 1 && sirt_scratch_bytes(g, nb, quarter, nullptr) > FP_NOALLOC_SCRATCH_BYTES)
+int fitting_chunk(const fp_geometry *g, Form form) {
+    int nb = sirt_max_chunk(g, form);
+    while (nb > 1 && sirt_scratch_bytes(g, nb, form, nullptr) > FP_NOALLOC_SCRATCH_BYTES)
         nb /= 2;
     return nb;
 }
@@ -75,15 +75,16 @@ extern "C" fp_status fp_sirt_step_noalloc(const fp_geometry *g, float *image,
             return FP_ERR_INVALID_ARG;
         }
     }
-    // the quarter-turn form where the geometry has it and one image's scratch
-    // fits, else the plain form
-    bool quarter = g->quarter;
-    int max_nb = fitting_chunk(g, quarter);
-    if (quarter && sirt_scratch_bytes(g, max_nb, true, nullptr) > FP_NOALLOC_SCRATCH_BYTES) {
-        quarter = false;
-        max_nb = fitting_chunk(g, false);
+    // the form fp_sirt_step takes where one image's scratch fits, else the
+    // next simpler one (octant, quarter-turn, plain)
+    Form form = sirt_form(g, batch);
+    int max_nb = fitting_chunk(g, form);
+    while (form != Form::kPlain &&
+           sirt_scratch_bytes(g, max_nb, form, nullptr) > FP_NOALLOC_SCRATCH_BYTES) {
+        form = form == Form::kOctant ? Form::kQuarter : Form::kPlain;
+        max_nb = fitting_chunk(g, form);
     }
-    const size_t need = sirt_scratch_bytes(g, max_nb, quarter, nullptr);
+    const size_t need = sirt_scratch_bytes(g, max_nb, form, nullptr);
     if (need > FP_NOALLOC_SCRATCH_BYTES) {
         set_error(std::string(fn) + ": one image needs " + std::to_string(need) +
                   " bytes of scratch, more than the fixed " +
@@ -92,6 +93,6 @@ extern "C" fp_status fp_sirt_step_noalloc(const fp_geometry *g, float *image,
     }
     void *p = nullptr;
     if ((st = scratch_address(g->device, &p, fn)) != FP_OK) return st;
-    return sirt_step_launch(g, image, sino_meas, relaxation, work, batch, max_nb, quarter, p,
+    return sirt_step_launch(g, image, sino_meas, relaxation, work, batch, max_nb, form, p,
                             static_cast<hipStream_t>(stream), fn);
 }

@@ -86,6 +86,8 @@ _lib.fp_sirt_scratch_bytes.argtypes = [_vp, ctypes.c_int32]
 _lib.fp_sirt_scratch_bytes.restype = ctypes.c_size_t
 _lib.fp_geometry_quarter_turn.argtypes = [_vp]
 _lib.fp_geometry_quarter_turn.restype = ctypes.c_int32
+_lib.fp_geometry_symmetry.argtypes = [_vp]
+_lib.fp_geometry_symmetry.restype = ctypes.c_int32
 _lib.fp_last_error.argtypes = []
 _lib.fp_last_error.restype = ctypes.c_char_p
 
@@ -93,7 +95,7 @@ EXPORTED = ("fp_geometry_create", "fp_geometry_create_desc", "fp_geometry_destro
             "fp_back_f64", "fp_forward_reference", "fp_back_reference", "fp_sirt_step", "fp_sirt_step_noalloc",
             "fp_sirt_prepare", "fp_sirt_step_multi",
             "fp_count_nonzero", "fp_sirt_scratch_bytes", "fp_geometry_device_bytes", "fp_geometry_quarter_turn",
-            "fp_last_error")
+            "fp_geometry_symmetry", "fp_last_error")
 
 
 class FanprojError(RuntimeError):
@@ -241,6 +243,10 @@ def fp_geometry_quarter_turn(handle) -> bool:
     return bool(_lib.fp_geometry_quarter_turn(handle))
 
 
+def fp_geometry_symmetry(handle) -> int:
+    return int(_lib.fp_geometry_symmetry(handle))
+
+
 # -- convenience wrapper --------------------------------------------------------
 
 class Geometry:
@@ -350,3 +356,10 @@ class Geometry:
     def quarter_turn(self) -> bool:
         """Whether FP32 projections run in the quarter-turn form."""
         return fp_geometry_quarter_turn(self.handle)
+
+    def symmetry(self) -> int:
+        """Order of the scan symmetry the FP32 projections use: 8 (quarter
+        turns and the diagonal reflection: the back projection evaluates
+        each entry for eight views, the forward for four), 4 (quarter turns)
+        or 1."""
+        return fp_geometry_symmetry(self.handle)

@@ -8,6 +8,9 @@ is checked here against the dense FP64 oracle (which evaluates every view on
 its own), against the plain form of the same scan (the views listed in
 reverse order, which the library does not recognise as quarter turns), for
 batches split over launches, SIRT, the adjoint identity and determinism.
+The scans here start at angles that the diagonal reflection does not map
+onto the view set (or have V % 8 == 4), so they take the quarter-turn form
+and not the octant form.
 """
 import numpy as np
 import pytest
@@ -48,7 +51,7 @@ def _kw(n, nv, nd, width, pitch=None, offset=0.0, pixel=1.0):
 
 @pytest.mark.parametrize("beam", ["flat", "arc", "parallel"])
 @pytest.mark.parametrize("n,nv,nd,width,pitch,offset", [
-    (64, 48, 130, 1.3, None, 0.0),      # aligned image, views from angle 0
+    (64, 48, 130, 1.3, None, 0.05),     # aligned image
     (37, 36, 77, 0.9, 0.8, 0.3),        # ragged tiles, odd cells, overlapping cells, offset views
     (1, 8, 9, 0.5, None, 0.1),          # one pixel
 ])
@@ -57,6 +60,7 @@ def test_against_dense_oracle(oracle_mod, fp, torch_cuda, beam, n, nv, nd, width
     kw, pitch = _kw(n, nv, nd, width, pitch, offset)
     og = oracle_mod.Geometry(**kw, det_spacing=pitch, mode=MODES[beam])
     gg = fp.Geometry(**kw, beam=beam, det_pitch=pitch)
+    assert gg.symmetry() == 4
     img = phantoms.uniform((n, n), 71, 0.0, 1.0)
     y = gg.forward(torch.from_numpy(img).cuda()).cpu().numpy()
     y_ref = og.forward(img.astype(np.float64), dense=True)
@@ -77,11 +81,12 @@ def test_matches_plain_form(fp, torch_cuda, beam):
     (launch chunks of two and one)."""
     torch = torch_cuda
     n, nv, nd = 160, 360, 330
-    kw, _ = _kw(n, nv, nd, 1.0)
+    kw, _ = _kw(n, nv, nd, 1.0, offset=np.pi / nv)   # half a view step
     gq = fp.Geometry(**kw, beam=beam)
     kw_rev = dict(kw, angles=kw["angles"][::-1].copy())
     gp = fp.Geometry(**kw_rev, beam=beam)
     assert gq.quarter_turn() and not gp.quarter_turn()
+    assert gq.symmetry() == 4
     imgs = torch.from_numpy(np.stack([phantoms.ellipses(n, 8, 80 + b) for b in range(3)])).cuda()
     yq = gq.forward(imgs)
     yp = gp.forward(imgs).flip(1)
@@ -101,9 +106,10 @@ def test_matches_plain_form(fp, torch_cuda, beam):
 
 def test_adjoint_and_sirt(oracle_mod, fp, torch_cuda):
     torch = torch_cuda
-    kw, _ = _kw(96, 120, 200, 1.1)
+    kw, _ = _kw(96, 120, 200, 1.1, offset=0.2)
     og = oracle_mod.Geometry(**kw)
     gg = fp.Geometry(**kw)
+    assert gg.symmetry() == 4
     c = torch.from_numpy(phantoms.uniform((96, 96), 73)).cuda()
     yv = torch.from_numpy(phantoms.uniform((120, 200), 74)).cuda()
     lhs = float((gg.forward(c).double() * yv.double()).sum())
