@@ -31,8 +31,10 @@ FLOPS_ACCUMULATE = 2
 def flops_per_entry(views_per_evaluation: int) -> float:
     """Algorithmic flops per non-zero entry when one evaluation of the entry
     (everything but its accumulate FMA) serves `views_per_evaluation` views:
-    4 in the quarter-turn form, where views v + k V/4 share the entries of
-    view v on the quarter-turned image, 1 in the plain form."""
+    8 in the octant form of the back projection, where views v + k V/4 and
+    their reflections across the image diagonal share the entries of view v
+    on the turned and reflected image, 4 in the quarter-turn form (turns
+    only), 1 in the plain form."""
     return (FLOPS_PER_ENTRY - FLOPS_ACCUMULATE) / views_per_evaluation + FLOPS_ACCUMULATE
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed / dual issue) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
@@ -121,21 +123,28 @@ def batch_rel_l2(og, outputs, seed=17):
             "sample": f"{len(got_f)} rays and {len(got_b)} pixels over the {nb} images"}
 
 
-def plain_form_pairs(scan, img, steps):
-    """Context: the same pair with the views listed in reverse order, which
-    the library does not recognise as quarter turns (the plain form, every
-    view evaluated on its own)."""
+def other_form_pairs(scan, img, steps, form):
+    """Context: the pair in another form.  "plain": the same views listed in
+    reverse order, which the library does not recognise as quarter turns
+    (every view evaluated on its own); "quarter-turn": the views shifted by
+    half a view step, a scan the quarter turns leave unchanged but the
+    diagonal reflection does not (each entry evaluated for four views)."""
     from paper_1907_10526_amd import fanproj
     kw = scan.kwargs()
-    kw["angles"] = kw["angles"][::-1].copy()
+    ang = kw["angles"]
+    if form == "plain":
+        kw["angles"], vpe = ang[::-1].copy(), 1
+        what = "views in reverse order: every view evaluated on its own"
+    else:
+        kw["angles"], vpe = ang + 0.5 * (ang[1] - ang[0]), 4
+        what = "views shifted by half a step: each entry evaluated for four views"
     g = fanproj.Geometry(**kw)
     try:
-        assert not g.quarter_turn()
+        assert g.symmetry() == vpe
         ms, _, _ = time_pairs(g, img, steps)
     finally:
         g.close()
-    return {"ms_per_pair": ms, "pairs_per_s": 1e3 / ms, "steps": steps,
-            "what": "views in reverse order: every view evaluated on its own"}
+    return {"ms_per_pair": ms, "pairs_per_s": 1e3 / ms, "steps": steps, "what": what}
 
 
 def parse():
@@ -152,8 +161,11 @@ def parse():
                    help="repeat the oracle sample until this much time has passed (at most 8 passes)")
     p.add_argument("--serve-jobs", type=int, default=1000,
                    help="jobs in the served-vs-plain comparison (0 skips it)")
-    p.add_argument("--serve-rates", type=float, nargs="+", default=[50.0, 30.0],
-                   help="mean arrivals per second of each served-vs-plain trace")
+    p.add_argument("--serve-loads", type=float, nargs="+", default=[0.9, 0.6],
+                   help="arrival rates of the served-vs-plain traces as fractions of the plain "
+                        "path's measured capacity (jobs/s with every job queued at once)")
+    p.add_argument("--serve-rates", type=float, nargs="+", default=None,
+                   help="arrival rates (jobs/s) instead of --serve-loads")
     p.add_argument("--serve-budget-gib", type=float, default=2.0,
                    help="device-memory budget of the serving loop")
     p.add_argument("--serve-step-work", type=float, default=4e9,
@@ -229,34 +241,49 @@ def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample, min_se
 
 def serving(args):
     """Served (continuous batching) vs plain (one job at a time) on the same
-    seeded arrival traces, at each rate of --serve-rates: SIRT jobs of
-    256/512/1024-pixel images, 180-1440 views, 2 x side cells, 20
-    iterations each.  Returns the record and, for the first rate, the final
-    iterates and sinograms of the first two 256 x 256, 180-view jobs (for the
-    oracle check of the CPU-baseline leg)."""
+    seeded arrival traces: SIRT jobs of 256/512/1024-pixel images, 180-1440
+    views, 2 x side cells, 20 iterations each.  The rates are --serve-rates,
+    or the fractions --serve-loads of the plain path's capacity, measured
+    first on 300 jobs of the same mix queued at once (seed 6).  Returns the
+    record and, for the first rate, the final iterates and sinograms of the
+    first two 256 x 256, 180-view jobs (for the oracle check of the
+    CPU-baseline leg)."""
     from paper_1907_10526_amd import serve
     budget = int(args.serve_budget_gib * (1 << 30))
     out = {"trace": f"{args.serve_jobs} jobs, Poisson arrivals (seed 5), image side "
                     "{256,512,1024}, views {180,360,720,1440}, cells 2 x side, source-centre "
                     "U[2,4] x side, magnification 1.5, 20 SIRT iterations, sinograms U[0, 4]",
            "hbm_budget_bytes": budget, "step_work_entries": args.serve_step_work, "rates": {}}
+    rates = args.serve_rates
+    if rates is None:
+        t0 = time.perf_counter()
+        cal = serve.latency_stats(serve.run_plain(serve.GpuExecutor(),
+                                                  serve.make_trace(300, 1e6, seed=6)))
+        cap = cal["throughput_jobs_per_s"]
+        out["plain_capacity_jobs_per_s"] = cap
+        rates = [load * cap for load in args.serve_loads]
+        print(f"serving: plain capacity {cap:.1f} jobs/s ({time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
     kept = None
-    for k, rate in enumerate(args.serve_rates):
+    for k, rate in enumerate(rates):
         trace = serve.make_trace(args.serve_jobs, rate, seed=5)
         check = [s.job_id for s in trace if s.n == 256 and s.n_views == 180][:2] if k == 0 else []
         ex = serve.GpuExecutor(keep_inputs=set(check))
         t0 = time.perf_counter()
         batched = serve.Server(ex, hbm_budget=budget, step_work=args.serve_step_work,
                                keep_outputs=set(check)).run(trace)
-        print(f"serving {rate:g}/s: batched loop done in {time.perf_counter() - t0:.1f} s",
+        print(f"serving {rate:.1f}/s: batched loop done in {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         plain = serve.run_plain(ex, trace)
-        print(f"serving {rate:g}/s: plain path done in {time.perf_counter() - t0:.1f} s",
+        print(f"serving {rate:.1f}/s: plain path done in {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
         bs, ps = serve.latency_stats(batched), serve.latency_stats(plain)
-        out["rates"][f"{rate:g}/s"] = {
-            "batched": bs, "plain": ps,
+        key = f"{rate:.1f}/s"
+        if args.serve_rates is None:
+            key = f"{args.serve_loads[k]:g} x capacity ({rate:.1f}/s)"
+        out["rates"][key] = {
+            "rate_jobs_per_s": rate, "batched": bs, "plain": ps,
             "p50_batched_vs_plain": bs["p50_s"] / ps["p50_s"],
             "p99_batched_vs_plain": bs["p99_s"] / ps["p99_s"]}
         if check:
@@ -338,11 +365,15 @@ def main():
     step_ms = fwd_ms + bck_ms
     ms_per_step = total_ms / K
 
-    views_per_eval = 4 if geom.quarter_turn() else 1
-    f_entry = flops_per_entry(views_per_eval)
-    flops = f_entry * nnz  # per launch (one projection)
+    # views one evaluated entry serves: the back projection uses the scan's
+    # whole symmetry (8: quarter turns and the diagonal reflection), the
+    # forward its quarter turns
+    sym = geom.symmetry()
+    vpe = {"forward": min(sym, 4), "back": sym}
+    flops_k = {k: flops_per_entry(v) * nnz for k, v in vpe.items()}   # per launch
     kernels = {"forward": float(fwd_ms.mean()), "back": float(bck_ms.mean())}
     dom = max(kernels, key=kernels.get)
+    flops, f_entry, views_per_eval = flops_k[dom], flops_per_entry(vpe[dom]), vpe[dom]
     achieved = flops / (kernels[dom] * 1e-3) / 1e12
     traffic = None
     if TRAFFIC["sources_sha256"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
@@ -353,10 +384,11 @@ def main():
                 "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
                 "flops_per_launch": flops, "entries_per_launch": nnz,
                 "flops_per_entry": f_entry, "views_per_entry_evaluation": views_per_eval,
-                "form": "quarter-turn" if views_per_eval == 4 else "plain",
+                "form": {8: "quarter-turn forward, octant back", 4: "quarter-turn"}.get(sym, "plain"),
                 "avg_ms": {k: round(v, 5) for k, v in kernels.items()},
-                "other_kernel_frac": {k: flops / (v * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
-                                      for k, v in kernels.items()}}
+                "views_per_entry_evaluation_by_kernel": vpe,
+                "frac_by_kernel": {k: flops_k[k] / (v * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
+                                   for k, v in kernels.items()}}
 
     out = {
         "metric": "projection pairs (A+A\u1d40)/sec at 512\u00b2\u00d7720 views; p99 job latency; "
@@ -385,7 +417,8 @@ def main():
     batch_out = None
     if not args.no_batch8:
         out["batch8"], batch_out = batched_pairs(geom, img, 8, max(2, K // 5))
-        out["plain_form"] = plain_form_pairs(scan, img, max(5, K // 2))
+        out["plain_form"] = other_form_pairs(scan, img, max(5, K // 2), "plain")
+        out["quarter_form"] = other_form_pairs(scan, img, max(5, K // 2), "quarter-turn")
 
     kept = None
     if args.serve_jobs > 0:

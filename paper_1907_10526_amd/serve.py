@@ -10,23 +10,27 @@ arrive over time with different image sizes, view counts and detector counts.
   budget and the slot limit allow (admission by free HBM);
 * an admitted job keeps its geometry tables, iterate, sinogram and scratch on
   the device until it finishes;
-* every step advances admitted jobs by one SIRT iteration in grouped launches
+* every step advances admitted jobs by SIRT iterations in grouped launches
   (``fp_sirt_step_multi``: the padded copies and forward residuals of up to
   12 jobs of different geometries in one launch each, then each job's back
   update), so jobs that arrive while others run join at the next step and
   their work overlaps on the device (continuous batching).  A job large enough
-  to fill the device by itself runs its iteration with the single-job kernels
-  instead, in the same stream;  A step takes the
-  admitted jobs, oldest first, whose summed work per iteration fits a budget
-  (always at least the oldest job): enough small jobs to fill the device, without
-  stretching an old job's iterations by the work of every younger one;
+  to fill the device by itself runs its iterations with the single-job kernels
+  instead, in the same stream;
+* a step fills a work budget with jobs in order of their remaining device
+  time less `aging` times the time they have spent in the system (shortest
+  remaining first, so a small job that arrives while a large one runs does
+  not wait for all of it, while a job's priority rises as it waits, so none
+  starves): one iteration each while the budget holds (the first job
+  always), several for a job that ends up alone;
 * finished jobs leave and free their memory for the queue.
 
 ``run_plain`` is the comparison path: one job at a time, in arrival order,
 with ``fp_sirt_step``.
 
-The scheduler only talks to an executor (``prepare``, ``step``, ``run_job``,
-``result``, ``release``)
+The scheduler only talks to an executor (``prepare``, ``step`` or ``launch``
+and ``wait``, ``run_job``, ``result``, ``release``; a step takes the jobs'
+handles and an iteration count per job)
 and a clock, so its admission and ordering logic can be tested on the CPU
 with a scripted executor and a simulated clock.
 """
@@ -99,12 +103,16 @@ def _view_groups(tiles: int, views: int, cus: int) -> int:
 def job_scratch_bytes(spec: JobSpec, cus: int = 256) -> int:
     """Device scratch one SIRT step of the job takes from the library's
     buffers: the padded image copies and the back projection's partial sums,
-    in the quarter-turn form (views a multiple of 4 over 2 pi) or the plain
-    one.  Equal to fp_sirt_scratch_bytes for the job's geometry."""
+    in the octant form (views a multiple of 8 over 2 pi from angle 0: views
+    0 .. nv/8 with eight sums per pixel), the quarter-turn form (a multiple
+    of 4: nv/4 views, four sums) or the plain one.  Equal to
+    fp_sirt_scratch_bytes for the job's geometry."""
     n, nv = spec.n, spec.n_views
     tiles = math.ceil(n / 16) * math.ceil(n / 32)
     copies = 4 * n * 2 * (n + 32)          # row-major and transposed padded copies
-    if nv % 4 == 0:
+    if nv % 8 == 0:
+        partial = 4 * _view_groups(tiles, nv // 8 + 1, cus) * 8 * n * n
+    elif nv % 4 == 0:
         partial = 4 * _view_groups(tiles, nv // 4, cus) * 4 * n * n
     else:
         g = _view_groups(tiles, nv, cus)
@@ -183,9 +191,10 @@ class Server:
 
     hbm_budget: bytes the admitted jobs may hold together (a job larger than
     the budget is admitted alone when nothing else runs); max_active: slot
-    limit; step_work: matrix entries one step may evaluate (the oldest job
-    always goes); keep_outputs: True, False or the job ids whose final
-    iterates ``run`` returns.  With an executor that reports ``available_bytes()`` (the
+    limit; step_work: matrix entries one step may evaluate (its first job
+    always goes); aging, rate, max_iters: the step plan (``plan``);
+    keep_outputs: True, False or the job ids whose final iterates ``run``
+    returns.  With an executor that reports ``available_bytes()`` (the
     device's free memory), a job is admitted only while its estimate also
     fits that less `reserve` bytes; finished jobs whose memory the executor
     still holds are flushed first.
@@ -202,16 +211,52 @@ class Server:
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
                  step_work: float = 4e9, clock=None, keep_outputs: bool = False,
-                 depth: int = 2, reserve: int = 256 << 20, burst: int = 4):
+                 depth: int = 2, reserve: int = 256 << 20, aging: float = 1.0,
+                 rate: float = 2e12, max_iters: int = 8):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.reserve = int(reserve)
-        self.burst = max(1, int(burst))
         self.max_active = int(max_active)
         self.step_work = float(step_work)
         self.clock = clock or RealClock()
         self.keep_outputs = keep_outputs
         self.depth = max(1, int(depth))
+        self.aging = float(aging)
+        self.rate = float(rate)
+        self.max_iters = max(1, int(max_iters))
+
+    def plan(self, active, now):
+        """Jobs and iteration counts of the next step.  Jobs are taken in
+        order of remaining device time (remaining work / `rate`) less `aging`
+        times their time in the system, one iteration each while the step's
+        work budget holds (the first job always; a later one that does not
+        fit is passed over for the next), so small jobs share the device; a
+        job that ends up alone gets more iterations (up to `max_iters` and
+        its remaining ones) while the budget still holds.  Returns
+        [(job, iterations)] in that order."""
+        def key(a):
+            rem = (a.spec.iters - a.done_iters) * job_iteration_work(a.spec)
+            return (rem / self.rate - self.aging * (now - a.spec.arrival), a.spec.arrival)
+        order = sorted(active, key=key)
+        counts, left = {}, self.step_work
+        for a in order:
+            w = job_iteration_work(a.spec)
+            if counts and w > left:
+                continue
+            counts[id(a)] = 1
+            left -= w
+            if left <= 0:
+                break
+        plan = [a for a in order if id(a) in counts]
+        if len(plan) == 1 and left > 0:
+            # a job alone: more of its iterations in the step (fewer host
+            # round trips); several jobs keep one iteration each, so that
+            # every iteration of the step still shares the device
+            a = plan[0]
+            w = job_iteration_work(a.spec)
+            extra = min(a.spec.iters - a.done_iters, self.max_iters) - 1
+            counts[id(a)] += max(0, min(extra, int(left // w)))
+        return [(a, counts[id(a)]) for a in plan]
 
     def run(self, trace) -> ServeResult:
         res = ServeResult()
@@ -265,30 +310,16 @@ class Server:
             res.peak_active = max(res.peak_active, len(active))
             res.peak_bytes = max(res.peak_bytes, used)
             if active:
-                # one SIRT iteration for the oldest admitted jobs that fit the
-                # step's work budget (first fit in admission order: the oldest
-                # job always goes, a job that does not fit leaves room for
-                # younger, smaller ones), in grouped launches
-                batch, work = [], 0.0
-                for a in active:
-                    w = job_iteration_work(a.spec)
-                    if batch and work + w > self.step_work:
-                        continue
-                    batch.append(a)
-                    work += w
-                handles = [a.handle for a in batch]
-                # with nobody waiting for admission, up to `burst` iterations
-                # of the batch go in one step (fewer host round trips)
-                iters = 1
-                if self.burst > 1 and not waiting:
-                    iters = min(self.burst, min(a.spec.iters - a.done_iters for a in batch))
+                plan = self.plan(active, clock.now())
+                handles = [a.handle for a, _ in plan]
+                iters = [k for _, k in plan]
                 fn = self.ex.launch if pipelined else self.ex.step
-                token = fn(handles, iters) if iters > 1 else fn(handles)
+                token = fn(handles, iters)
                 res.steps += 1
-                res.batch_sizes.append(len(batch))
+                res.batch_sizes.append(len(plan))
                 finishing = []
-                for a in batch:
-                    a.done_iters += iters
+                for a, k in plan:
+                    a.done_iters += k
                     if a.done_iters >= a.spec.iters:
                         finishing.append(a)
                 if finishing:
@@ -424,15 +455,17 @@ class GpuExecutor:
             t.record_stream(self.stream)
         return (g, x, y, w)
 
-    def step(self, handles, iters: int = 1) -> None:
+    def step(self, handles, iters=1) -> None:
         self.launch(handles, iters).synchronize()
 
-    def launch(self, handles, iters: int = 1):
-        """Queue `iters` SIRT iterations of the jobs; returns an event recorded
-        after them."""
+    def launch(self, handles, iters=1):
+        """Queue SIRT iterations of the jobs (`iters`: one count for all, or
+        one per job: iteration k runs the jobs with more than k); returns an
+        event recorded after them."""
+        counts = [iters] * len(handles) if isinstance(iters, int) else list(iters)
         with self.torch.cuda.stream(self.stream):
-            for _ in range(iters):
-                self._queue(handles)
+            for k in range(max(counts, default=0)):
+                self._queue([h for h, c in zip(handles, counts) if c > k])
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
         return ev

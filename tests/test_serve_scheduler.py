@@ -24,13 +24,23 @@ class FakeExecutor:
         self.log.append(("prepare", spec.job_id, self.clock.now()))
         return spec.job_id
 
+    def iteration_costs(self, handles, iters):
+        """Device time of each iteration of a step: iteration k runs the jobs
+        with more than k iterations."""
+        counts = _counts(handles, iters)
+        out = []
+        for k in range(max(counts)):
+            hs = [h for h, c in zip(handles, counts) if c > k]
+            tot = sum(self.work(self.live[h]) for h in hs)
+            big = max(self.work(self.live[h]) for h in hs)
+            out.append(max(tot / self.width, big))
+        return out
+
     def step(self, handles, iters=1):
-        tot = sum(self.work(self.live[h]) for h in handles)
-        big = max(self.work(self.live[h]) for h in handles)
-        for _ in range(iters):
-            self.clock.advance(self.overhead + max(tot / self.width, big))
+        for t in self.iteration_costs(handles, iters):
+            self.clock.advance(self.overhead + t)
         self.log.append(("step", tuple(handles), self.clock.now()))
-        self.step_iters.append(iters)
+        self.step_iters.append(_counts(handles, iters))
 
     def run_job(self, h, iters):
         for _ in range(iters):
@@ -42,6 +52,10 @@ class FakeExecutor:
     def release(self, h):
         self.live.pop(h)
         self.log.append(("release", h, self.clock.now()))
+
+
+def _counts(handles, iters):
+    return [iters] * len(handles) if isinstance(iters, int) else list(iters)
 
 
 def _trace(count=40, rate=50.0, seed=5, iters=20):
@@ -131,33 +145,68 @@ def test_late_arrivals_join_running_batch():
     assert res.finished[1] < res.finished[0]
 
 
-def test_step_work_budget_keeps_fifo_priority():
-    """With a per-step work budget, each step holds the oldest admitted job
-    and younger jobs in admission order while their work fits."""
+def test_step_plan_follows_priority_and_budget():
+    """Each step takes jobs in order of remaining device time less the aging
+    credit of their time in the system, as many iterations each as the work
+    budget holds (the first job at least one); no job runs past its last
+    iteration, and a step with more than one job stays within the budget."""
     clock = serve.SimClock()
     ex = FakeExecutor(clock)
     trace = _trace(count=30, rate=200.0, iters=8)
     big = max(serve.job_iteration_work(s) for s in trace)
-    res = serve.Server(ex, hbm_budget=1 << 40, step_work=big, clock=clock).run(trace)
+    srv = serve.Server(ex, hbm_budget=1 << 40, step_work=big, clock=clock)
+    res = srv.run(trace)
     assert len(res.latency) == 30
-    order = {j: k for k, j in enumerate(res.order)}
-    iterating, steps = set(), {}
-    step_iters = iter(ex.step_iters)
-    for kind, handles, _ in ex.log:
-        if kind == "prepare":
-            iterating.add(handles)
-        elif kind == "step":
-            ks = [order[h] for h in handles]
-            assert ks == sorted(ks)                           # admission order
-            assert ks[0] == min(order[h] for h in iterating)  # the oldest unfinished job
-            n_it = next(step_iters)
-            for h in handles:
-                steps[h] = steps.get(h, 0) + n_it
-                assert steps[h] <= trace[h].iters
-                if steps[h] == trace[h].iters:
-                    iterating.discard(h)
-            tot = sum(serve.job_iteration_work(trace[h]) for h in handles)
-            assert len(handles) == 1 or tot <= big
+    done = {}
+    for (kind, handles, _), counts in zip([e for e in ex.log if e[0] == "step"], ex.step_iters):
+        assert all(c >= 1 for c in counts) and all(c <= srv.max_iters for c in counts)
+        work = 0.0
+        for h, c in zip(handles, counts):
+            done[h] = done.get(h, 0) + c
+            assert done[h] <= trace[h].iters
+            work += c * serve.job_iteration_work(trace[h])
+        assert len(handles) == 1 or work <= big
+    assert all(done[s.job_id] == s.iters for s in trace)
+
+
+def test_plan_order():
+    """Shortest remaining first; waiting raises a job's priority; with a
+    large aging weight the order is arrival order."""
+    srv = serve.Server(None, step_work=1e30, rate=1e9, aging=1.0, max_iters=1)
+    big = serve.JobSpec(0, 0.0, 1024, 1440, 2048, 3000.0, 4500.0, iters=20)
+    small = serve.JobSpec(1, 0.5, 256, 180, 512, 700.0, 1050.0, iters=20)
+    a_big = serve._Active(big, "big", 0, 0.0)
+    a_small = serve._Active(small, "small", 0, 0.5)
+    order = lambda now, s=srv: [a.handle for a, _ in s.plan([a_big, a_small], now)]
+    assert order(0.5) == ["small", "big"]
+    # the big job's remaining time: 20 x 9.06e9 entries at 1e9/s = 181 s;
+    # a small job that arrives 190 s after it no longer overtakes it
+    late = serve._Active(serve.JobSpec(2, 190.0, 256, 180, 512, 700.0, 1050.0, iters=20),
+                         "late", 0, 190.0)
+    assert [a.handle for a, _ in srv.plan([a_big, late], 200.0)] == ["big", "late"]
+    fifo = serve.Server(None, step_work=1e30, rate=1e9, aging=1e9, max_iters=1)
+    assert order(0.5, fifo) == ["big", "small"]
+    # the budget: the first job always goes, a later one only if it fits
+    tight = serve.Server(None, step_work=1.0, rate=1e9, aging=1.0, max_iters=4)
+    plan = tight.plan([a_big, a_small], 0.5)
+    assert [(a.handle, k) for a, k in plan] == [("small", 1)]
+    roomy = serve.Server(None, step_work=3.5 * serve.job_iteration_work(small), rate=1e9,
+                         aging=1.0, max_iters=8)
+    assert [(a.handle, k) for a, k in roomy.plan([a_small], 0.5)] == [("small", 3)]
+
+
+def test_small_job_overtakes_a_large_one():
+    """A small job arriving while a large one runs finishes long before the
+    large one (shortest remaining first), which still completes."""
+    clock = serve.SimClock()
+    ex = FakeExecutor(clock)
+    big = serve.JobSpec(0, 0.0, 1024, 1440, 2048, 3000.0, 4500.0, iters=20)
+    small = serve.JobSpec(1, 0.05, 256, 180, 512, 700.0, 1050.0, iters=20)
+    res = serve.Server(ex, hbm_budget=1 << 40, clock=clock).run([big, small])
+    assert res.finished[1] < res.finished[0]
+    c2 = serve.SimClock()
+    plain = serve.run_plain(FakeExecutor(c2), [big, small], clock=c2)
+    assert res.latency[1] < 0.5 * plain.latency[1]
 
 
 class SaturatingExecutor(FakeExecutor):
@@ -170,8 +219,9 @@ class SaturatingExecutor(FakeExecutor):
         self.sat = sat
 
     def step(self, handles, iters=1):
-        tot = sum(self.work(self.live[h]) for h in handles)
-        for _ in range(iters):
+        counts = _counts(handles, iters)
+        for k in range(max(counts)):
+            tot = sum(self.work(self.live[h]) for h, c in zip(handles, counts) if c > k)
             self.clock.advance(self.overhead + max(tot, self.sat) / self.width)
         self.log.append(("step", tuple(handles), self.clock.now()))
 
@@ -204,13 +254,11 @@ class AsyncFakeExecutor(FakeExecutor):
         self.busy_until = 0.0
 
     def launch(self, handles, iters=1):
-        tot = sum(self.work(self.live[h]) for h in handles)
-        big = max(self.work(self.live[h]) for h in handles)
         self.clock.advance(self.host)
         start = max(self.busy_until, self.clock.now())
-        self.busy_until = start + iters * max(tot / self.width, big)
+        self.busy_until = start + sum(self.iteration_costs(handles, iters))
         self.log.append(("step", tuple(handles), self.busy_until))
-        self.step_iters.append(iters)
+        self.step_iters.append(_counts(handles, iters))
         return self.busy_until
 
     def wait(self, token):
@@ -249,8 +297,7 @@ def test_pipelined_loop_is_complete_and_within_budget():
             live.discard(x)
             used -= sizes[x]
         else:
-            n_it = next(step_iters)
-            for h in x:
+            for h, n_it in zip(x, next(step_iters)):
                 assert h in live
                 steps[h] = steps.get(h, 0) + n_it
     assert all(steps[s.job_id] == s.iters for s in trace)
@@ -274,17 +321,17 @@ def test_pipelining_overlaps_host_and_device():
     assert serve.latency_stats(pipe)["mean_s"] < serve.latency_stats(sync)["mean_s"]
 
 
-def test_bursts_only_when_nobody_waits():
-    """With an empty admission queue a step may advance its jobs by several
-    iterations at once (never past a job's last); a job waiting for admission
-    turns bursts off."""
+def test_lone_jobs_take_several_iterations_per_step():
+    """A job alone takes as many iterations per step as the work budget
+    holds (at most max_iters), so a small job needs few host round trips."""
     clock = serve.SimClock()
     ex = FakeExecutor(clock)
     trace = _trace(count=12, rate=5.0, iters=10)
-    res = serve.Server(ex, hbm_budget=1 << 40, clock=clock, burst=4).run(trace)
+    res = serve.Server(ex, hbm_budget=1 << 40, clock=clock, max_iters=4).run(trace)
     assert len(res.latency) == 12
-    assert max(ex.step_iters) == 4 and min(ex.step_iters) >= 1
+    counts = [c for cs in ex.step_iters for c in cs]
+    assert max(counts) == 4 and min(counts) >= 1
     clock = serve.SimClock()
     ex1 = FakeExecutor(clock)
-    serve.Server(ex1, hbm_budget=1 << 40, clock=clock, burst=1).run(trace)
-    assert set(ex1.step_iters) == {1}
+    serve.Server(ex1, hbm_budget=1 << 40, clock=clock, max_iters=1).run(trace)
+    assert {c for cs in ex1.step_iters for c in cs} == {1}
