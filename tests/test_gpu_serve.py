@@ -75,7 +75,7 @@ def test_admission_estimate_bounds_device_memory(torch_cuda, n, views):
     held = g.device_bytes() + 4 * (x.numel() + y.numel() + w.numel()) + scratch
     est = serve.job_device_bytes(spec, cus)
     print(f"{n}^2 x {views}: estimate {est} bytes, held {held} bytes "
-          f"(quarter-turn form {g.quarter_turn()})", flush=True)
+          f"(symmetry order {g.symmetry()})", flush=True)
     assert est >= held
     ex.release((g, x, y, w))
     ex.flush()

@@ -116,7 +116,7 @@ def test_sirt50_large_matches_stored_oracle(fp, torch_cuda):
     e_norm = abs(np.sqrt(np.sum(xc * xc)) / np.sqrt(float(ref["sumsq"])) - 1.0)
     print(f"large SIRT-{int(ref['iters'])} vs oracle: {len(pix)} pixels rel-L2 {e_pix:.3e}, "
           f"central rows {e_rows:.3e}, central column {e_col:.3e}, norm {e_norm:.3e} "
-          f"(quarter-turn form {g.quarter_turn()})", flush=True)
+          f"(symmetry order {g.symmetry()})", flush=True)
     assert max(e_pix, e_rows, e_col, e_norm) <= 1e-4
 
 
