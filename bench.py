@@ -45,16 +45,17 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of each entry point at this workload (quarter-turn
-# form), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this script, each
+# forward, octant back), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this script, each
 # scaled by what the same counter reads for a 256 MiB device copy in the same
 # run (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); the summary and commands are in
 # profiles/.  Valid only for the kernel sources they were taken on: `traffic`
 # is reported as null once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "1ab180a6c41a96293a84ff254f053e96a852f89eb6da597443b9c60f469e3976",
-    # entry-point brackets: padded copies + forward walk; back + rotation finalize
-    "bytes_per_launch": {"forward": 26954000, "back": 201260000},
-    "profile": "profiles/cnsf_quarter_pair_512x720x1024.md",
+    "sources_sha256": "9bc0e54f5bd0efe1b9896aa0d9484177a3ad7aa9092d3561b90e687df7e51549",
+    # entry-point brackets: padded copies + quarter-turn forward walk; octant
+    # back + its finalize
+    "bytes_per_launch": {"forward": 50178496, "back": 113502848},
+    "profile": "profiles/cnsf_symmetric_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",
                    "back_flat_f32.hip"]
