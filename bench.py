@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # profiles/.  Valid only for the kernel sources they were taken on: `traffic`
 # is reported as null once the hash of those sources differs.
 TRAFFIC = {
-    "sources_sha256": "9bc0e54f5bd0efe1b9896aa0d9484177a3ad7aa9092d3561b90e687df7e51549",
+    "sources_sha256": "0b3ea1357023944a0f9d0b9b6ce8eafe55055e3de49bd6398a74aa3f613fd695",
     # entry-point brackets: padded copies + quarter-turn forward walk; octant
     # back + its finalize
-    "bytes_per_launch": {"forward": 50178496, "back": 113502848},
+    "bytes_per_launch": {"forward": 29725280, "back": 113501536},
     "profile": "profiles/cnsf_symmetric_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",

@@ -117,6 +117,9 @@ struct DevGeom {
     // Octant form only (nv = quarter_views / 2 + 1 base views of a scan of
     // 4 quarter_views views): views per quarter turn; 0 in the other forms.
     int quarter_views;
+    // Upper bound on the forward walk's window width in pixels (a launch
+    // heuristic: a wider window is still walked correctly, by the loop).
+    int fwd_window;
     int beam;                // FP_FAN_FLAT, FP_FAN_ARC or FP_PARALLEL
     double pixel;            // delta
     double dsc, dsd;         // source-centre, source-detector distances
@@ -243,8 +246,9 @@ hipError_t launch_back_quarter_beam(const DevGeom &g, BackMode mode, int nb, con
 // Q/2 are their own reflections and serve four views.  Modes kPlain and
 // kSirtUpdate, `partial` of back_octant_work_bytes(g) bytes.  (The forward
 // projection of such a scan runs in the quarter-turn form: its ray walk
-// reads one pixel value per non-zero entry in either form, and those reads,
-// not the entry arithmetic, bound it.)
+// reads one pixel value per non-zero entry in either form, and an eight-view
+// walk, with twice the reads and accumulators per evaluated entry, measured
+// slower.)
 size_t back_octant_work_bytes(const DevGeom &g);
 hipError_t launch_back_octant(const DevGeom &g, BackMode mode, const float *sino, float *img,
                               float *partial, const float *col_w, float relaxation,

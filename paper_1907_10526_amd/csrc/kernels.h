@@ -300,7 +300,10 @@ __device__ __forceinline__ void walk_block(const RayWalk<Real> &w, double Xb, Re
     // walked backwards)
     const size_t stride = w.row_stride;
     const Real *rowp = w.base + (size_t)rb * stride;
-    const Real *mrowp = S == 4 ? w.base + (size_t)(w.nr - 1 - rb) * stride : rowp;
+    // (S = 4: the image is square, so nr is the same for every lane: saying
+    // so keeps the mirrored row's pointer in scalar registers)
+    const int nr_u = S == 4 ? __builtin_amdgcn_readfirstlane(w.nr) : w.nr;
+    const Real *mrowp = S == 4 ? w.base + (size_t)(nr_u - 1 - rb) * stride : rowp;
 
     // the window's pixel values of row r (rows rp and mp) starting at p
     auto load = [&](Real (&cv)[K][T], const Real *rp, const Real *mp, unsigned p, int r) {
@@ -410,7 +413,7 @@ __device__ void walk_block_wide(const RayWalk<Real> &w, int T, double X, Real sp
 // window width is the wave's largest need over the block: the blur grows
 // with depth along the ray, so blocks on the source side take narrower
 // windows than the ray's deepest row would.
-template <typename Real, int NB, FwdMode MODE, int S>
+template <typename Real, int NB, FwdMode MODE, int S, int TMAX>
 __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r_first, int r1,
                                           Real (&acc)[NB * S], int &nonzero) {
     constexpr int K = NB * S;
@@ -435,14 +438,24 @@ __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r_first, i
             case 2: walk_block<Real, NB, 2, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
             case 3: walk_block<Real, NB, 3, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
             case 4: walk_block<Real, NB, 4, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
-            case 5: walk_block<Real, NB, 5, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
-            case 6: walk_block<Real, NB, 6, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero); break;
+            // (windows wider than TMAX take the loop: the quarter-turn form
+            // holds four loads per pixel, and a narrower widest window keeps
+            // its registers for more waves)
+            case 5:
+                if constexpr (TMAX >= 5) {
+                    walk_block<Real, NB, 5, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero);
+                    break;
+                }
+                [[fallthrough]];
+            case 6:
+                if constexpr (TMAX >= 6) {
+                    walk_block<Real, NB, 6, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero);
+                    break;
+                }
+                [[fallthrough]];
             case 7:
             case 8:
-                // (the quarter-turn form holds four loads per pixel: its
-                // widest unrolled window is 6, which keeps its registers
-                // for more waves)
-                if constexpr (S == 1) {
+                if constexpr (TMAX >= 8) {
                     walk_block<Real, NB, 8, MODE, S>(w, Xb, sp_top, hcp, rb, re, blk, nonzero);
                     break;
                 }
@@ -473,7 +486,10 @@ __device__ __forceinline__ void walk_rows(const RayWalk<Real> &w, int r_first, i
 // (mirrored x = W - 1 - x, a read running backwards), so the reads q = 0, 1
 // share row r and q = 2, 3 row n-1-r (RayWalk::qoff).  The outputs are
 // [nb][4][nv][nd]: image b's sinogram of 4 nv views.
-template <typename Real, int NB, FwdMode MODE, int S>
+// TMAX: the widest window walked with an unrolled row (wider ones take the
+// loop of walk_block_wide): 8 for the plain walk, 6 or 4 for the quarter-turn
+// walk (4 when no window of the geometry is wider, DevGeom::fwd_window).
+template <typename Real, int NB, FwdMode MODE, int S, int TMAX = (S == 1 ? 8 : 6)>
 __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_block,
                                               const Real *__restrict__ copies,
                                               Real *__restrict__ out,
@@ -481,12 +497,15 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
                                               const Real *__restrict__ y_meas,
                                               const Real *__restrict__ row_w) {
     const RayTables<Real> &tab = ray_tables<Real>(G);
-    // S = 4: the work-group's two halves walk the first and the second half
-    // of the row blocks of the same rays (waves w and w + 2 hold the same
-    // rays, so their row ranges agree)
+    // S = 4: the work-group's kParts parts walk consecutive shares of the row
+    // blocks of the same rays (waves w and w + kRays / 64 hold the same rays,
+    // so their row ranges agree)
     constexpr int kParts = S == 4 ? kFwdQuarterParts : 1;
     constexpr int kRays = kFwdThreads / kParts;
-    const int part = (int)threadIdx.x / kRays;
+    // (kRays is a multiple of the wave size, so the part is uniform across
+    // the wave; saying so keeps the row loop's pointers and bounds in scalar
+    // registers)
+    const int part = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kRays);
     const int m_thread = m_block * kRays + (int)threadIdx.x % kRays;
     const bool active = m_thread < G.nd;
     // threads past the last cell walk the last ray (their wave needs them for
@@ -621,27 +640,30 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     for (int k = 0; k < NB * S; ++k) acc[k] = 0;
     int nonzero = 0;
     if constexpr (kParts == 1) {
-        if (r0 <= r1) walk_rows<Real, NB, MODE, S>(w, r0, r1, acc, nonzero);
+        if (r0 <= r1) walk_rows<Real, NB, MODE, S, TMAX>(w, r0, r1, acc, nonzero);
     } else {
         if (r0 <= r1) {
+            // part p walks row blocks [p per, (p + 1) per)
             const int blocks = (r1 - r0) / kFwdBlockRows + 1;
-            const int r_mid = r0 + (blocks + 1) / 2 * kFwdBlockRows;   // first row of part 1
-            if (part == 0)
-                walk_rows<Real, NB, MODE, S>(w, r0, min(r1, r_mid - 1), acc, nonzero);
-            else if (r_mid <= r1)
-                walk_rows<Real, NB, MODE, S>(w, r_mid, r1, acc, nonzero);
+            const int per = (blocks + kParts - 1) / kParts;
+            const int ra = r0 + part * per * kFwdBlockRows;
+            const int rb = min(r1, ra + per * kFwdBlockRows - 1);
+            if (ra <= rb) walk_rows<Real, NB, MODE, S, TMAX>(w, ra, rb, acc, nonzero);
         }
-        // part 1 hands its sums to part 0 through LDS (fixed order: part 0's
-        // rows first)
-        __shared__ Real part_acc[NB * S][kRays];
-        if (part == 1) {
+        // the other parts hand their sums to part 0 through LDS (fixed
+        // order: part 0's rows first)
+        __shared__ Real part_acc[kParts - 1][NB * S][kRays];
+        if (part > 0) {
 #pragma unroll
-            for (int k = 0; k < NB * S; ++k) part_acc[k][threadIdx.x - kRays] = acc[k];
+            for (int k = 0; k < NB * S; ++k)
+                part_acc[part - 1][k][threadIdx.x - part * kRays] = acc[k];
         }
         __syncthreads();
-        if (part == 1) return;
+        if (part > 0) return;
 #pragma unroll
-        for (int k = 0; k < NB * S; ++k) acc[k] += part_acc[k][threadIdx.x];
+        for (int q = 0; q < kParts - 1; ++q)
+#pragma unroll
+            for (int k = 0; k < NB * S; ++k) acc[k] += part_acc[q][k][threadIdx.x];
     }
     if (!active) return;
     const Real wbr = tab.wb()[ray];
@@ -674,13 +696,13 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     }
 }
 
-template <typename Real, int NB, FwdMode MODE, int S>
+template <typename Real, int NB, FwdMode MODE, int S, int TMAX = (S == 1 ? 8 : 6)>
 // (the quarter-turn walk of one image at 6 waves per SIMD, 80 VGPRs)
 __global__ __launch_bounds__(kFwdThreads, S == 1 ? min_waves(NB, sizeof(Real)) : NB == 1 ? 6 : 1) void forward_kernel(
     DevGeom G, const Real *__restrict__ copies,
     Real *__restrict__ out, int *__restrict__ counts, const Real *__restrict__ y_meas,
     const Real *__restrict__ row_w) {
-    forward_block<Real, NB, MODE, S>(G, blockIdx.x, blockIdx.y, copies, out, counts, y_meas,
+    forward_block<Real, NB, MODE, S, TMAX>(G, blockIdx.x, blockIdx.y, copies, out, counts, y_meas,
                                      row_w);
 }
 
