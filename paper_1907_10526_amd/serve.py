@@ -211,7 +211,7 @@ class Server:
 
     def __init__(self, executor, hbm_budget: int = 2 << 30, max_active: int = 64,
                  step_work: float = 4e9, clock=None, keep_outputs: bool = False,
-                 depth: int = 2, reserve: int = 256 << 20, aging: float = 1.0,
+                 depth: int = 2, reserve: int = 256 << 20, aging: float = 3.0,
                  rate: float = 2e12, max_iters: int = 8):
         self.ex = executor
         self.budget = int(hbm_budget)

@@ -202,7 +202,10 @@ def test_small_job_overtakes_a_large_one():
     ex = FakeExecutor(clock)
     big = serve.JobSpec(0, 0.0, 1024, 1440, 2048, 3000.0, 4500.0, iters=20)
     small = serve.JobSpec(1, 0.05, 256, 180, 512, 700.0, 1050.0, iters=20)
-    res = serve.Server(ex, hbm_budget=1 << 40, clock=clock).run([big, small])
+    # (rate: the fake device's entries per second, so that remaining times
+    # and waiting times are on one clock)
+    rate = serve.job_iteration_work(big) / ex.work(big)
+    res = serve.Server(ex, hbm_budget=1 << 40, clock=clock, rate=rate).run([big, small])
     assert res.finished[1] < res.finished[0]
     c2 = serve.SimClock()
     plain = serve.run_plain(FakeExecutor(c2), [big, small], clock=c2)
