@@ -224,16 +224,20 @@ fp_status fp_sirt_step(const fp_geometry *g, float *image,
 /* The SIRT step of fp_sirt_step for callers that cannot allocate device
  * memory: code under HIP graph capture, serving loops that must not call
  * hipMalloc, harnesses that forbid it.  Arguments, layouts, result and errors
- * are those of fp_sirt_step (the same kernels, so the same values), with
- * three differences:
+ * are those of fp_sirt_step (the same kernels in the same form, so the same
+ * values, wherever that form's scratch fits the array below), with three
+ * differences:
  *   - the geometry's SIRT weights must already exist (fp_sirt_prepare or an
  *     earlier fp_sirt_step built them); otherwise FP_ERR_INVALID_ARG;
  *   - the launches' scratch (padded image copies, view-group partial sums)
  *     is a fixed array of FP_NOALLOC_SCRATCH_BYTES in device memory that the
  *     library holds on every device it runs on until the process ends; the
- *     batch is processed in chunks that fit it, and a geometry whose single
- *     image needs more gives FP_ERR_UNSUPPORTED (about 2048 x 2048 images
- *     and up);
+ *     batch is processed in chunks that fit it; where one image's scratch in
+ *     fp_sirt_step's form does not fit, the next simpler form whose scratch
+ *     fits runs (octant, quarter-turn, plain: equal to FP32 rounding; at
+ *     2048 x 2048 the plain form), and a geometry whose single image needs
+ *     more than the array in every form gives FP_ERR_UNSUPPORTED (about
+ *     2900 x 2900 images and up);
  *   - the call allocates nothing and waits on nothing on the host, and every
  *     call on one device shares that array: calls that can overlap on the
  *     device (different streams, or different host threads without ordering)
