@@ -55,6 +55,11 @@ TRAFFIC = {
     # entry-point brackets: padded copies + quarter-turn forward walk; octant
     # back + its finalize
     "bytes_per_launch": {"forward": 29725280, "back": 113501536},
+    # VALU instruction utilisation of each entry point's main kernel, from the
+    # same profile's SQ_INSTS_VALU: wave-instructions per CU per cycle over
+    # the kernel's duration (1.0 = the FP32 VALU peak, one wave64 instruction
+    # per CU per cycle)
+    "valu_utilization": {"forward": 0.70, "back": 0.63},
     "profile": "profiles/cnsf_symmetric_pair_512x720x1024.md",
 }
 TRAFFIC_SOURCES = ["kernels.h", "fanproj_internal.h", "forward.hip", "back_launch.h",
@@ -392,12 +397,14 @@ def main():
     ex_flops = {k: flops_per_entry(v) * nnz for k, v in vpe.items()}   # per launch
     rate = lambda f, ms: f / (ms * 1e-3) / 1e12
     achieved = rate(flops, kernels[dom])
-    traffic = None
+    traffic = valu = None
     if TRAFFIC["sources_sha256"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
         traffic = TRAFFIC["bytes_per_launch"].get(dom)
+        valu = TRAFFIC["valu_utilization"].get(dom)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                 "traffic_unit": "bytes per launch", "traffic_profile": TRAFFIC["profile"],
+                "valu_utilization": valu,
                 "flops_per_entry": FLOPS_PER_ENTRY, "entries_per_launch": nnz,
                 "flops_per_launch": flops,
                 "form": {8: "quarter-turn forward, octant back", 4: "quarter-turn"}.get(sym, "plain"),
