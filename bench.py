@@ -167,11 +167,12 @@ def parse():
                    help="repeat the oracle sample until this much time has passed (at most 8 passes)")
     p.add_argument("--serve-jobs", type=int, default=1000,
                    help="jobs in the served-vs-plain comparison (0 skips it)")
-    p.add_argument("--serve-loads", type=float, nargs="+", default=[0.9, 0.6],
-                   help="arrival rates of the served-vs-plain traces as fractions of the plain "
-                        "path's measured capacity (jobs/s with every job queued at once)")
-    p.add_argument("--serve-rates", type=float, nargs="+", default=None,
-                   help="arrival rates (jobs/s) instead of --serve-loads")
+    p.add_argument("--serve-rates", type=float, nargs="*", default=[50.0],
+                   help="arrival rates (jobs/s) of served-vs-plain traces (the served-stream "
+                        "workload's 50/s by default)")
+    p.add_argument("--serve-loads", type=float, nargs="*", default=[0.9],
+                   help="further traces at these fractions of the plain path's measured "
+                        "capacity (jobs/s with every job queued at once): near capacity")
     p.add_argument("--serve-budget-gib", type=float, default=2.0,
                    help="device-memory budget of the serving loop")
     p.add_argument("--serve-step-work", type=float, default=4e9,
@@ -248,9 +249,10 @@ def cpu_baseline(scan, img, sino, y_gpu_rows, z_gpu_part, n_views_sample, min_se
 def serving(args):
     """Served (continuous batching) vs plain (one job at a time) on the same
     seeded arrival traces: SIRT jobs of 256/512/1024-pixel images, 180-1440
-    views, 2 x side cells, 20 iterations each.  The rates are --serve-rates,
-    or the fractions --serve-loads of the plain path's capacity, measured
-    first on 300 jobs of the same mix queued at once (seed 6).  Returns the
+    views, 2 x side cells, 20 iterations each.  The rates are --serve-rates
+    (50/s: the served-stream workload), then the fractions --serve-loads of
+    the plain path's capacity, measured first on 300 jobs of the same mix
+    queued at once (seed 6).  Returns the
     record and, for the first rate, the final iterates and sinograms of the
     first two 256 x 256, 180-view jobs (for the oracle check of the
     CPU-baseline leg)."""
@@ -260,18 +262,19 @@ def serving(args):
                     "{256,512,1024}, views {180,360,720,1440}, cells 2 x side, source-centre "
                     "U[2,4] x side, magnification 1.5, 20 SIRT iterations, sinograms U[0, 4]",
            "hbm_budget_bytes": budget, "step_work_entries": args.serve_step_work, "rates": {}}
-    rates = args.serve_rates
-    if rates is None:
+    rates = [(f"{r:g}/s", r) for r in (args.serve_rates or [])]
+    if args.serve_loads:
         t0 = time.perf_counter()
         cal = serve.latency_stats(serve.run_plain(serve.GpuExecutor(),
                                                   serve.make_trace(300, 1e6, seed=6)))
         cap = cal["throughput_jobs_per_s"]
         out["plain_capacity_jobs_per_s"] = cap
-        rates = [load * cap for load in args.serve_loads]
+        rates += [(f"{load:g} x capacity ({load * cap:.1f}/s)", load * cap)
+                  for load in args.serve_loads]
         print(f"serving: plain capacity {cap:.1f} jobs/s ({time.perf_counter() - t0:.1f} s)",
               file=sys.stderr, flush=True)
     kept = None
-    for k, rate in enumerate(rates):
+    for k, (key, rate) in enumerate(rates):
         trace = serve.make_trace(args.serve_jobs, rate, seed=5)
         check = [s.job_id for s in trace if s.n == 256 and s.n_views == 180][:2] if k == 0 else []
         ex = serve.GpuExecutor(keep_inputs=set(check))
@@ -285,9 +288,6 @@ def serving(args):
         print(f"serving {rate:.1f}/s: plain path done in {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
         bs, ps = serve.latency_stats(batched), serve.latency_stats(plain)
-        key = f"{rate:.1f}/s"
-        if args.serve_rates is None:
-            key = f"{args.serve_loads[k]:g} x capacity ({rate:.1f}/s)"
         out["rates"][key] = {
             "rate_jobs_per_s": rate, "batched": bs, "plain": ps,
             "p50_batched_vs_plain": bs["p50_s"] / ps["p50_s"],
