@@ -31,6 +31,14 @@ __host__ __device__ constexpr int padded_width(int nx, int ny) {
     return (nx > ny ? nx : ny) + 2 * kFwdPad;
 }
 constexpr int kFwdMaxUnrolled = 8;   // widest row window with an unrolled variant
+// A ray marches along the image axis closest to its direction, except that
+// a ray whose smaller direction component is at least kFwdAxisShare of the
+// larger (within 3 degrees of a diagonal) takes the axis most rays of its
+// wave take; its cross axis then still advances s' by at least
+// kFwdCrossMin delta per pixel (kFwdAxisShare / sqrt(1 + kFwdAxisShare^2),
+// rounded down), against delta / sqrt(2) for the closest axis.
+constexpr double kFwdAxisShare = 0.9;
+constexpr double kFwdCrossMin = 0.6689;
 // Threads per ray of the quarter-turn form's forward: each walks half of the
 // ray's row blocks (a work-group then covers kFwdThreads / 2 rays), which,
 // compiled for 6 waves per SIMD, made it 6 % faster at 512^2 x 720 x 1024

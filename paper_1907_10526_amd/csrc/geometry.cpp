@@ -280,10 +280,11 @@ extern "C" fp_status fp_geometry_create_desc(const fp_geometry_desc *desc, fp_ge
     d.r64 = RayTables<double>{};
     d.tile_cells = d_tiles;
     // The walk's window spans the support |s'| < hab + hc along the cross
-    // axis, where s' advances by at least delta / sqrt(2) per pixel and
+    // axis, where s' advances by at least kFwdCrossMin delta per pixel and
     // hab <= delta / sqrt(2): at most floor(2 hq) + 1 pixels with
-    // hq = (0.7072 delta + hc_max) / (0.7071 delta).
-    d.fwd_window = (int)std::floor(2.0 * (0.7072 * delta + hc_max) / (0.7071 * delta)) + 1;
+    // hq = (0.7072 delta + hc_max) / (kFwdCrossMin delta).
+    d.fwd_window =
+        (int)std::floor(2.0 * (0.7072 * delta + hc_max) / (kFwdCrossMin * delta)) + 1;
     d.back_cap = 0;
     for (int cap : kBackCaps)
         if (max_cells + 2 * kBackPad <= cap) { d.back_cap = cap; break; }

@@ -558,8 +558,19 @@ __device__ __forceinline__ void forward_block(const DevGeom &G, int v, int m_blo
     }
     const double wpx = -wy, wpy = wx;
     // March along the image axis closest to the ray; the other ("cross")
-    // axis then advances s' by at least delta / sqrt(2) per pixel.
-    const bool by_rows = fabs(wy) >= fabs(wx);
+    // axis then advances s' by at least delta / sqrt(2) per pixel.  A wave
+    // whose rays would march along different axes walks the union of both
+    // row ranges with the wider window (the heaviest waves of a view, next
+    // to the diagonal), so rays near a diagonal follow the axis of most of
+    // their wave (its cross axis still advances s' by kFwdCrossMin delta
+    // per pixel).  Every lane of the wave runs this (lanes past the last
+    // cell walk the last ray).
+    const double awx = fabs(wx), awy = fabs(wy);
+    bool by_rows = awy >= awx;
+    {
+        const bool most = __popcll(__ballot(by_rows)) * 2 >= 64;
+        if (fmin(awx, awy) >= kFwdAxisShare * fmax(awx, awy)) by_rows = most;
+    }
     const int nq = by_rows ? G.nx : G.ny, nr = by_rows ? G.ny : G.nx;
 
     RayWalk<Real> w;
