@@ -153,6 +153,83 @@ def other_form_pairs(scan, img, steps, form):
     return {"ms_per_pair": ms, "pairs_per_s": 1e3 / ms, "steps": steps, "what": what}
 
 
+def large_scan(steps):
+    """Context: the 2048^2 x 1440-view x 2048-cell scan (source-centre 4000,
+    source-detector 6000, cell width 1; views uniform over 2 pi, symmetry
+    order 8): geometry creation, one forward + back pair and one SIRT step of
+    one image.  Returns the record and the inputs and outputs that the
+    CPU-baseline leg samples against the oracle."""
+    import torch
+    from paper_1907_10526_amd import fanproj, phantoms, workloads
+    scan = workloads.LARGE
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g = fanproj.Geometry(**scan.kwargs())
+    torch.cuda.synchronize()
+    t_geom = time.perf_counter() - t
+    try:
+        img_np = workloads.phantom(scan)
+        img = torch.from_numpy(img_np).cuda()
+        ms_pair, y, _ = time_pairs(g, img, steps)
+        sino_np = phantoms.uniform((scan.n_views, scan.n_det), 14, 0.0, 1.0)
+        z = g.back(torch.from_numpy(sino_np).cuda())
+        # SIRT steps from zero on the image's own sinogram (the first call
+        # builds the row and column weights and is not timed)
+        x = torch.zeros_like(img)
+        work = torch.empty_like(y)
+        g.sirt_step(x, y, 1.0, work)
+        stream = torch.cuda.current_stream()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            g.sirt_step(x, y, 1.0, work)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms_sirt = start.elapsed_time(stop) / steps
+        nnz = g.count_nonzero()
+        sym = g.symmetry()
+        data = (img_np, y.cpu().numpy(), sino_np, z.cpu().numpy())
+    finally:
+        g.close()
+    rec = {"workload": "2048x2048 image (pixel 1), 1440 views over 2pi, 2048 flat-detector cells "
+                       "of width 1, source-centre 4000, source-detector 6000, 20 seeded ellipses",
+           "symmetry": sym, "geometry_create_ms": 1e3 * t_geom, "steps": steps,
+           "ms_per_pair": ms_pair, "pairs_per_s": 1e3 / ms_pair, "sirt_step_ms": ms_sirt,
+           "entries_per_projection": nnz,
+           "algorithmic_tflops_pair": 2 * FLOPS_PER_ENTRY * nnz / (ms_pair * 1e-3) / 1e12}
+    return rec, data
+
+
+def large_rel_l2(data, seed=19):
+    """rel-L2 of the large scan's forward and back projections against the
+    FP64 oracle on sampled rays and pixels (part of the CPU-baseline leg)."""
+    import oracle
+    from paper_1907_10526_amd import workloads
+    img, y, sino, z = data
+    og = oracle.Geometry(**workloads.LARGE.kwargs())
+    nv, nd = y.shape
+    rng = np.random.default_rng(seed)
+    x = img.astype(np.float64)
+    got_f, ref_f = [], []
+    for _ in range(12):
+        v, m = int(rng.integers(0, nv)), int(rng.integers(nd // 4, 3 * nd // 4))
+        got_f.append(y[v, m])
+        ref_f.append(og.forward_ray(x, v, m))
+    s64 = sino.astype(np.float64)
+    got_b, ref_b = [], []
+    for _ in range(16):
+        i, j = int(rng.integers(0, z.shape[1])), int(rng.integers(0, z.shape[0]))
+        got_b.append(z[j, i])
+        ref_b.append(og.back_pixel(s64, i, j))
+
+    def rel(a, r):
+        return float(np.linalg.norm(np.subtract(a, r)) / np.linalg.norm(r))
+    return {"forward": rel(got_f, ref_f), "back": rel(got_b, ref_b),
+            "sample": f"{len(got_f)} rays of the phantom's sinogram, {len(got_b)} pixels of the "
+                      "back projection of a U[0, 1] sinogram"}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -160,7 +237,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-batch8", action="store_true",
-                   help="skip the 8-image batch measurement (profiled runs)")
+                   help="skip the context measurements: the 8-image batch, the other forms "
+                        "and the large scan (profiled runs)")
     p.add_argument("--cpu-sample-views", type=int, default=720,
                    help="views of the workload the FP64 oracle is timed on")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -445,11 +523,12 @@ def main():
         "roofline": roofline,
     }
 
-    batch_out = None
+    batch_out = large_out = None
     if not args.no_batch8:
         out["batch8"], batch_out = batched_pairs(geom, img, 8, max(2, K // 5))
         out["plain_form"] = other_form_pairs(scan, img, max(5, K // 2), "plain")
         out["quarter_form"] = other_form_pairs(scan, img, max(5, K // 2), "quarter-turn")
+        out["large"], large_out = large_scan(max(3, K // 10))
 
     kept = None
     if args.serve_jobs > 0:
@@ -471,6 +550,8 @@ def main():
             import oracle
             out["batch8"]["rel_l2_vs_fp64"] = batch_rel_l2(oracle.Geometry(**scan.kwargs()),
                                                            batch_out)
+        if large_out is not None:
+            out["large"]["rel_l2_vs_fp64"] = large_rel_l2(large_out)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
