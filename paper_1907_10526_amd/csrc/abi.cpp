@@ -56,19 +56,30 @@ int quarter_max_chunk(const fp_geometry *g) {
     return std::max(1, std::min(kQuarterMaxChunk, back_max_batch<float>(g->dev_quarter) / 4));
 }
 
+// Free events of the marks, per device (never destroyed: marks held by
+// static objects are released during exit).
+struct MarkEvents {
+    std::mutex mu;
+    std::vector<std::vector<hipEvent_t>> free;   // [device]
+};
+MarkEvents &mark_events() {
+    static MarkEvents *m = new MarkEvents;
+    return *m;
+}
+
 // Device scratch of the launches (the forward's padded image copies, the
 // back projection's view-group partials, the grouped SIRT buffers).  Each
 // device keeps a set of buffers for the life of the process.  A call takes a
 // buffer that no other host thread is enqueuing with, makes its stream wait
-// for the buffer's last use (an event recorded on the stream that last used
-// it) and records that event again after its launches, so reuse across
-// calls, streams and threads is ordered on the device with no host
-// synchronisation and no allocation in steady state.  A buffer grows (after
-// its last use has finished) when a call needs more than it holds.
+// for the mark of the buffer's last use and, after its launches, hands the
+// buffer its own mark (the one mark the call records, finish_call).  Reuse
+// across calls, streams and threads is so ordered on the device with no host
+// synchronisation and no allocation in steady state.  A buffer grows (after its last use has
+// finished) when a call needs more than it holds.
 struct ScratchSlot {
     void *ptr = nullptr;
     size_t bytes = 0;
-    hipEvent_t last = nullptr;
+    MarkPtr last;   // mark of the last use (null: none pending)
     bool busy = false;
 };
 std::mutex g_scratch_mu;
@@ -94,12 +105,12 @@ ScratchSlot *take_slot(int dev, size_t bytes) {
 
 class Scratch {
   public:
-    Scratch(int dev, size_t bytes, hipStream_t s) : stream_(s) {
+    Scratch(int dev, size_t bytes, hipStream_t s) : dev_(dev), stream_(s) {
         slot_ = take_slot(dev, bytes);
-        if (!slot_->last) err_ = hipEventCreateWithFlags(&slot_->last, hipEventDisableTiming);
-        if (err_ == hipSuccess && slot_->bytes < bytes) {
+        if (slot_->bytes < bytes) {
             // grow: wait for the buffer's last use, then replace it
-            err_ = hipEventSynchronize(slot_->last);
+            if (slot_->last) err_ = hipEventSynchronize(slot_->last->ev);
+            slot_->last.reset();
             if (err_ == hipSuccess && slot_->ptr) err_ = hipFree(slot_->ptr);
             if (err_ == hipSuccess) {
                 slot_->ptr = nullptr;
@@ -109,10 +120,20 @@ class Scratch {
                 else slot_->ptr = nullptr;
             }
         }
-        if (err_ == hipSuccess) err_ = hipStreamWaitEvent(s, slot_->last, 0);
+        if (err_ == hipSuccess && slot_->last) err_ = hipStreamWaitEvent(s, slot_->last->ev, 0);
     }
+    // The call's mark, recorded after its launches (see finish_call).
+    void set_mark(const MarkPtr &m) { mark_ = m; marked_ = true; }
     ~Scratch() {
-        if (err_ == hipSuccess) (void)hipEventRecord(slot_->last, stream_);
+        if (err_ == hipSuccess) {
+            // (a call that ends early records its own mark here)
+            if (!marked_) mark_ = record_mark(dev_, stream_);
+            if (!mark_) {
+                // no mark: the buffer is free once this stream's work is done
+                if (hipStreamSynchronize(stream_) != hipSuccess) (void)hipGetLastError();
+            }
+            slot_->last = mark_;
+        }
         std::lock_guard<std::mutex> lock(g_scratch_mu);
         slot_->busy = false;
     }
@@ -124,9 +145,20 @@ class Scratch {
 
   private:
     ScratchSlot *slot_ = nullptr;
+    int dev_;
     hipStream_t stream_;
     hipError_t err_ = hipSuccess;
+    MarkPtr mark_;
+    bool marked_ = false;
 };
+
+// The end of a call that launched work for `g` on `s`: one mark, kept by the
+// call's scratch buffer (if any) and by the geometry.
+void finish_call(const fp_geometry *g, hipStream_t s, Scratch *scratch) {
+    const MarkPtr m = record_mark(g->device, s);
+    if (scratch) scratch->set_mark(m);
+    note_use(g, s, m);
+}
 
 fp_status scratch_error(const char *fn, hipError_t e) {
     (void)hipGetLastError();
@@ -177,28 +209,52 @@ fp_status ensure_weights(fp_geometry *g, hipStream_t stream) {
 
 }  // namespace
 
-void note_use(const fp_geometry *gc, hipStream_t s) {
+Mark::~Mark() {
+    if (!ev) return;
+    MarkEvents &me = mark_events();
+    std::lock_guard<std::mutex> lock(me.mu);
+    if ((int)me.free.size() <= dev) me.free.resize(dev + 1);
+    me.free[dev].push_back(ev);
+}
+
+MarkPtr record_mark(int dev, hipStream_t s) {
+    hipEvent_t ev = nullptr;
+    {
+        MarkEvents &me = mark_events();
+        std::lock_guard<std::mutex> lock(me.mu);
+        if ((int)me.free.size() > dev && !me.free[dev].empty()) {
+            ev = me.free[dev].back();
+            me.free[dev].pop_back();
+        }
+    }
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming | hipEventDisableSystemFence) !=
+                   hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    auto m = std::make_shared<Mark>();
+    m->ev = ev;
+    m->dev = dev;
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;   // (the event goes back to the free list)
+    }
+    return m;
+}
+
+void note_use(const fp_geometry *gc, hipStream_t s, const MarkPtr &m) {
     fp_geometry *g = const_cast<fp_geometry *>(gc);
     std::lock_guard<std::mutex> lock(g->use_mu);
-    for (auto &u : g->uses)
-        if (u.first == s) {
-            if (hipEventRecord(u.second, s) != hipSuccess) {
-                (void)hipGetLastError();
-                g->untracked = true;
-            }
-            return;
-        }
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
+    if (!m) {
         g->untracked = true;
         return;
     }
-    if (hipEventRecord(ev, s) != hipSuccess) {
-        (void)hipGetLastError();
-        g->untracked = true;
-    }
-    g->uses.emplace_back(s, ev);
+    for (auto &u : g->uses)
+        if (u.first == s) {
+            u.second = m;
+            return;
+        }
+    g->uses.emplace_back(s, m);
 }
 
 void set_error(const std::string &msg) { g_last_error = msg; }
@@ -248,7 +304,7 @@ fp_status forward_impl(const fp_geometry *gc, const Real *image, Real *sino, int
                 if (e != hipSuccess) return device_error(fn, e);
                 b0 += nb;
             }
-            note_use(g, s);
+            finish_call(g, s, &work);
             return FP_OK;
         }
     }
@@ -263,7 +319,7 @@ fp_status forward_impl(const fp_geometry *gc, const Real *image, Real *sino, int
         if (e != hipSuccess) return device_error(fn, e);
         b0 += nb;
     }
-    note_use(g, s);
+    finish_call(g, s, &work);
     return FP_OK;
 }
 
@@ -299,7 +355,7 @@ fp_status back_impl(const fp_geometry *gc, const Real *sino, Real *image, int32_
             hipError_t e = launch_back_octant(g->dev_octant, BackMode::kPlain, sino, image,
                                               partial.get(), nullptr, 0.0f, s);
             if (e != hipSuccess) return device_error(fn, e);
-            note_use(g, s);
+            finish_call(g, s, &partial);
             return FP_OK;
         }
         if (g->quarter) {
@@ -314,7 +370,7 @@ fp_status back_impl(const fp_geometry *gc, const Real *sino, Real *image, int32_
                 if (e != hipSuccess) return device_error(fn, e);
                 b0 += nb;
             }
-            note_use(g, s);
+            finish_call(g, s, &partial);
             return FP_OK;
         }
     }
@@ -330,7 +386,7 @@ fp_status back_impl(const fp_geometry *gc, const Real *sino, Real *image, int32_
         if (e != hipSuccess) return device_error(fn, e);
         b0 += nb;
     }
-    note_use(g, s);
+    finish_call(g, s, &partial);
     return FP_OK;
 }
 
@@ -376,7 +432,7 @@ fp_status reference_impl(const fp_geometry *g, bool forward, const double *in, d
     const hipError_t e = launch_reference(g, forward, in, out, batch, quad ? quad : 16,
                                           static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_error(fn, e);
-    note_use(g, static_cast<hipStream_t>(stream));
+    finish_call(g, static_cast<hipStream_t>(stream), nullptr);
     return FP_OK;
 }
 
@@ -504,7 +560,7 @@ extern "C" fp_status fp_sirt_step(const fp_geometry *g_const, float *image, cons
     if (scratch.status() != hipSuccess) return scratch_error("fp_sirt_step", scratch.status());
     st = sirt_step_launch(g, image, sino_meas, relaxation, work, batch, max_nb, form,
                           scratch.raw(), s, "fp_sirt_step");
-    if (st == FP_OK) note_use(g, s);
+    if (st == FP_OK) finish_call(g, s, &scratch);
     return st;
 }
 
@@ -647,6 +703,10 @@ extern "C" fp_status fp_sirt_step_multi(const fp_sirt_job *jobs, int32_t n_jobs,
             }
         }
     }
-    for (int k = 0; k < n_jobs; ++k) note_use(jobs[k].geometry, s);
+    {
+        const MarkPtr m = record_mark(dev, s);
+        scratch.set_mark(m);
+        for (int k = 0; k < n_jobs; ++k) note_use(jobs[k].geometry, s, m);
+    }
     return FP_OK;
 }

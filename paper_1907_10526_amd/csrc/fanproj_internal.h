@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -316,6 +317,22 @@ constexpr int kMultiMaxCap = 256;
 // of multi_copies_bytes and multi_partial_bytes bytes.
 hipError_t launch_sirt_multi(const MultiArgs &args, hipStream_t stream);
 
+// A point recorded on a stream after one call's launches (one event per
+// call, abi.cpp): the call's scratch buffer and its geometries keep it, and
+// whoever needs that work finished (the buffer's next user on another
+// stream, the memory of a destroyed geometry) waits for it.  The events are
+// created without the system-scope fence (they order work on the device and
+// tell the host that work has finished; nothing reads the results through
+// them) and go back to a per-device free list when the last holder lets go.
+struct Mark {
+    hipEvent_t ev = nullptr;
+    int dev = 0;
+    ~Mark();
+};
+using MarkPtr = std::shared_ptr<Mark>;
+// Records a mark on `s` (device `dev` current); nullptr if that fails.
+MarkPtr record_mark(int dev, hipStream_t s);
+
 }  // namespace fanproj
 
 struct fp_geometry {
@@ -350,12 +367,12 @@ struct fp_geometry {
     float *row_w = nullptr;        // [nv][nd]
     float *col_w = nullptr;        // [ny][nx]
     size_t weight_bytes = 0, row_cap = 0, col_cap = 0;
-    // The streams that launched work on the geometry, each with an event
-    // recorded after its latest launches: fp_geometry_destroy waits for these
-    // (not for the whole device) before freeing the tables.  untracked: an
-    // event could not be created, so destroy waits for the device.
+    // The streams that launched work on the geometry, each with the mark
+    // recorded after its latest launches: the memory of a destroyed geometry
+    // is reused only after these (not after the whole device).  untracked: a
+    // mark could not be recorded, so destroy waits for the device.
     std::mutex use_mu;
-    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+    std::vector<std::pair<hipStream_t, fanproj::MarkPtr>> uses;
     bool untracked = false;
 };
 
@@ -414,15 +431,16 @@ fp_status ensure_f64_tables(fp_geometry *g);
 // Device memory of geometries (pool.cpp): pool_alloc takes an idle block of
 // a destroyed geometry that fits (waiting for the work queued with it) or
 // allocates one; *capacity receives the block's size, which pool_release
-// needs.  pool_release hands blocks back with the events of the work still
-// queued against them (the pool owns the events from then on); it does not
-// wait.  Device `dev` must be current for both.
+// needs.  pool_release hands blocks back with the marks of the work still
+// queued against them; it does not wait.  Device `dev` must be current for
+// both.
 hipError_t pool_alloc(int dev, size_t bytes, void **out, size_t *capacity);
 void pool_release(int dev, const std::vector<std::pair<void *, size_t>> &blocks,
-                  const std::vector<hipEvent_t> &after);
-// Records an event after the work just queued on `s` for the geometry (its
-// device current), for fp_geometry_destroy.
-void note_use(const fp_geometry *g, hipStream_t s);
+                  const std::vector<MarkPtr> &after);
+// Keeps `m`, recorded after the work just queued on `s` for the geometry, as
+// that stream's latest use of it (a null mark makes destroy wait for the
+// device).
+void note_use(const fp_geometry *g, hipStream_t s, const MarkPtr &m);
 // Thread-local error text used by fp_last_error.
 void set_error(const std::string &msg);
 void clear_error();

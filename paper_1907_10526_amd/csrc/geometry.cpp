@@ -329,11 +329,11 @@ extern "C" fp_status fp_geometry_destroy(fp_geometry *g) {
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess && cur != g->device) e = hipSetDevice(g->device);
     if (e == hipSuccess) {
-        // The blocks go back to the pool with the events of the work queued
+        // The blocks go back to the pool with the marks of the work queued
         // with the geometry (the latest launches on every stream that used
         // it); nothing waits here.  Without a complete record of that work,
         // wait for the device instead.
-        std::vector<hipEvent_t> after;
+        std::vector<MarkPtr> after;
         {
             std::lock_guard<std::mutex> lock(g->use_mu);
             for (auto &u : g->uses) after.push_back(u.second);

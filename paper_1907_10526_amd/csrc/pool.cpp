@@ -19,13 +19,10 @@ namespace {
 constexpr size_t kPoolIdleCap = size_t(1) << 30;
 
 struct EventSet {
-    std::vector<hipEvent_t> events;
-    ~EventSet() {
-        for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    }
+    std::vector<MarkPtr> marks;
     void wait() const {
-        for (hipEvent_t e : events)
-            if (hipEventSynchronize(e) != hipSuccess) (void)hipGetLastError();
+        for (const MarkPtr &m : marks)
+            if (m && hipEventSynchronize(m->ev) != hipSuccess) (void)hipGetLastError();
     }
 };
 
@@ -81,9 +78,9 @@ hipError_t pool_alloc(int dev, size_t bytes, void **out, size_t *capacity) {
 }
 
 void pool_release(int dev, const std::vector<std::pair<void *, size_t>> &blocks,
-                  const std::vector<hipEvent_t> &after) {
+                  const std::vector<MarkPtr> &after) {
     auto set = std::make_shared<EventSet>();
-    set->events = after;   // owned from here on
+    set->marks = after;
     std::vector<IdleBlock> spill;
     {
         std::lock_guard<std::mutex> lock(g_pool_mu);
