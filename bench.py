@@ -49,15 +49,12 @@ PEAK_HBM_GBS = 8000.0
 # scaled by what the same counter reads for a 256 MiB device copy in the same
 # run (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); the summary and commands are in
 # profiles/.  Valid only for the kernel sources they were taken on: `traffic`
-# is reported as null once the hash of those sources differs.  (The hash
-# below is of sources whose gfx950 assembly of the forward and back kernels
-# is identical to that of the profiled sources; the change between them was
-# host-side declarations in the shared header.)
+# is reported as null once the hash of those sources differs.
 TRAFFIC = {
     "sources_sha256": "fed6574cb584bdd4f516dacc82fb68acba1aeef39159fc10eac6871937679fec",
     # entry-point brackets: padded copies + quarter-turn forward walk; octant
     # back + its finalize
-    "bytes_per_launch": {"forward": 29727104, "back": 113503168},
+    "bytes_per_launch": {"forward": 29727232, "back": 113501920},
     # VALU instruction utilisation of each entry point's main kernel, from the
     # same profile's SQ_INSTS_VALU: wave-instructions per CU per cycle over
     # the kernel's duration in the kernel trace of this script's default run,
