@@ -155,6 +155,27 @@ def other_form_pairs(scan, img, steps, form):
     return {"ms_per_pair": ms, "pairs_per_s": 1e3 / ms, "steps": steps, "what": what}
 
 
+def sirt_steps(geom, img, steps):
+    """Context: the SIRT step (fp_sirt_step: forward residual and back update,
+    one image) on the workload's geometry, from zero on the image's own
+    sinogram; the first call builds the weights and is not timed."""
+    import torch
+    y = geom.forward(img)
+    x = torch.zeros_like(img)
+    work = torch.empty_like(y)
+    geom.sirt_step(x, y, 1.0, work)
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        geom.sirt_step(x, y, 1.0, work)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    return {"ms": ms, "steps_per_s": 1e3 / ms, "steps": steps}
+
+
 def large_scan(steps):
     """Context: the 2048^2 x 1440-view x 2048-cell scan (source-centre 4000,
     source-detector 6000, cell width 1; views uniform over 2 pi, symmetry
@@ -542,6 +563,7 @@ def main():
         out["plain_form"] = other_form_pairs(scan, img, max(5, K // 2), "plain")
         out["quarter_form"] = other_form_pairs(scan, img, max(5, K // 2), "quarter-turn")
         out["large"], large_out = large_scan(max(3, K // 10))
+        out["sirt_step"] = sirt_steps(geom, img, max(5, K // 10))
 
     kept = None
     if args.serve_jobs > 0:
